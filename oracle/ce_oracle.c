@@ -1,0 +1,470 @@
+/*
+ * ce_oracle.c -- plain FP64 CPU reference of the conditional-entropy (CE)
+ * search over period P and period derivative Pdot (Katz et al.,
+ * arXiv:2006.06866, Sec. 2.3 "Conditional Entropy Implementation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP path.
+ *
+ * Every function is written for readability: one trial at a time, the fold of
+ * Eq. (3) point by point, the entropy of Eq. (4) term by term.  Arithmetic is
+ * IEEE double; build with -O2 -ffp-contract=off and without fast-math so the
+ * operation sequence below is exactly what executes.
+ *
+ * Readings of the paper taken here (the paper is silent on these points):
+ *   - time origin: t0 = the earliest epoch of the curve, dt = t - t0;
+ *   - magnitude normalisation: the curve's magnitudes are mapped linearly onto
+ *     [0, 1] by their min and max and cut into n_mag equal-width bins; the
+ *     median/std scaling of Sec. 2.3 is affine and so leaves these bins alone;
+ *   - right edges (m = m_max, phase rounding up to 1) fall in the last bin;
+ *   - empty histogram cells contribute nothing to Eq. (4);
+ *   - the minimum over the grid is the first strict minimum in flat order
+ *     flat = q * n_periods + p (Pdot index q outer, period index p inner);
+ *   - a curve whose epochs or magnitudes are not all finite is invalid: its
+ *     best index is -1, its CE values and best CE are NaN.
+ *
+ * Parity pins: every function here is pinned by the CPU tests (hand-counted
+ * histograms, exact dyadic folds, closed-form entropies, the library Shannon
+ * entropy identity, brute force over tiny grids, injected-signal recovery).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* ---------------------------------------------------------------------------
+ * Sec. 2.3: magnitudes normalised per light curve, then binned into n_mag
+ * equal-width magnitude bins.  Writes bin[k] in [0, n_mag).  Returns 0, or
+ * ORACLE_EINVAL for n <= 0 / n_mag < 1, or 1 if a magnitude is not finite.
+ * ------------------------------------------------------------------------- */
+int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
+                       int32_t *bin)
+{
+    if (n <= 0 || n_mag < 1 || !mags || !bin)
+        return ORACLE_EINVAL;
+    double lo = mags[0], hi = mags[0];
+    for (int64_t k = 0; k < n; ++k) {
+        if (!isfinite(mags[k]))
+            return 1;
+        if (mags[k] < lo) lo = mags[k];
+        if (mags[k] > hi) hi = mags[k];
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        if (hi == lo) {
+            bin[k] = 0;          /* constant curve: one magnitude bin */
+            continue;
+        }
+        double u = (mags[k] - lo) / (hi - lo); /* normalised to [0, 1] */
+        int32_t j = (int32_t)(u * (double)n_mag);
+        if (j >= n_mag) j = n_mag - 1;          /* m == m_max */
+        bin[k] = j;
+    }
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Eq. (3): the quadratic phase fold.  With x = dt / P the folded phase is
+ *     phi = frac( x - (1/2) * Pdot * x^2 ),
+ * which is Eq. (3) divided through by P.  1/P is taken once per trial by a
+ * correctly rounded division; (1/2)*Pdot is exact.  The square of x is formed
+ * first and the Pdot term is applied with one fused multiply-add.
+ * Returns the phase bin in [0, n_phase); a phase that rounds up to 1 falls in
+ * the last bin.
+ * ------------------------------------------------------------------------- */
+static int32_t fold_bin(double dt, double inv_p, double half_pdot,
+                        int32_t n_phase)
+{
+    double x = dt * inv_p;
+    double x2 = x * x;
+    double y = fma(-half_pdot, x2, x);
+    double phi = y - floor(y);
+    int32_t b = (int32_t)(phi * (double)n_phase);
+    if (b >= n_phase) b = n_phase - 1;
+    return b;
+}
+
+/* The classic P-only fold (Pdot absent): phi = frac(dt / P). */
+static int32_t fold_bin_ponly(double dt, double inv_p, int32_t n_phase)
+{
+    double y = dt * inv_p;
+    double phi = y - floor(y);
+    int32_t b = (int32_t)(phi * (double)n_phase);
+    if (b >= n_phase) b = n_phase - 1;
+    return b;
+}
+
+/* Exposed for the exact-arithmetic fold tests. */
+int32_t ce_oracle_fold_bin(double dt, double period, double pdot,
+                           int32_t n_phase)
+{
+    return fold_bin(dt, 1.0 / period, 0.5 * pdot, n_phase);
+}
+
+/* ---------------------------------------------------------------------------
+ * Eq. (4): H_c = sum_{i,j} p(m_i, phi_j) ln( p(phi_j) / p(m_i, phi_j) ),
+ * with p(m_i, phi_j) = c[i][j] / N and p(phi_j) = sum_i c[i][j] / N.
+ * counts is [n_mag][n_phase] (magnitude bin i outer, phase bin j inner).
+ * Phase bin outer, magnitude bin inner; cells with c = 0 are skipped.
+ * ------------------------------------------------------------------------- */
+double ce_oracle_entropy(const uint32_t *counts, int32_t n_mag,
+                         int32_t n_phase)
+{
+    double total = 0.0;
+    for (int32_t i = 0; i < n_mag; ++i)
+        for (int32_t j = 0; j < n_phase; ++j)
+            total += (double)counts[(int64_t)i * n_phase + j];
+    if (total <= 0.0)
+        return NAN;
+    double h = 0.0;
+    for (int32_t j = 0; j < n_phase; ++j) {
+        double col = 0.0;
+        for (int32_t i = 0; i < n_mag; ++i)
+            col += (double)counts[(int64_t)i * n_phase + j];
+        double p_phi = col / total;
+        for (int32_t i = 0; i < n_mag; ++i) {
+            uint32_t c = counts[(int64_t)i * n_phase + j];
+            if (c == 0)
+                continue;
+            double p_joint = (double)c / total;
+            h += p_joint * log(p_phi / p_joint);
+        }
+    }
+    return h;
+}
+
+/* Per-curve preparation shared by the search entry points below. */
+typedef struct {
+    int64_t n;
+    double *dt;        /* t - t0 */
+    int32_t *mbin;     /* magnitude bin of each epoch */
+    int valid;
+} curve_prep;
+
+static int prep_curve(const double *t, const double *m, int64_t n,
+                      int32_t n_mag, curve_prep *cp)
+{
+    cp->n = n;
+    cp->valid = 1;
+    cp->dt = (double *)malloc((size_t)n * sizeof(double));
+    cp->mbin = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!cp->dt || !cp->mbin)
+        return ORACLE_ENOMEM;
+    double t0 = t[0];
+    for (int64_t k = 0; k < n; ++k) {
+        if (!isfinite(t[k]))
+            cp->valid = 0;
+        if (t[k] < t0) t0 = t[k];
+    }
+    for (int64_t k = 0; k < n; ++k)
+        cp->dt[k] = t[k] - t0;
+    if (ce_oracle_mag_bins(m, n, n_mag, cp->mbin) != ORACLE_OK)
+        cp->valid = 0;
+    return ORACLE_OK;
+}
+
+static void free_prep(curve_prep *cp)
+{
+    free(cp->dt);
+    free(cp->mbin);
+    cp->dt = NULL;
+    cp->mbin = NULL;
+}
+
+/* Histogram of one trial: counts[n_mag][n_phase] is cleared and filled. */
+static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
+                         int ponly, int32_t n_phase, int32_t n_mag,
+                         uint32_t *counts)
+{
+    memset(counts, 0, (size_t)n_mag * (size_t)n_phase * sizeof(uint32_t));
+    for (int64_t k = 0; k < cp->n; ++k) {
+        int32_t b = ponly ? fold_bin_ponly(cp->dt[k], inv_p, n_phase)
+                          : fold_bin(cp->dt[k], inv_p, half_pdot, n_phase);
+        counts[(int64_t)cp->mbin[k] * n_phase + b] += 1;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Histogram of one (curve, P, Pdot) trial, as used by Eq. (4).
+ * times/mags hold the curve's n epochs; counts is [n_mag][n_phase].
+ * Returns 0, ORACLE_EINVAL, or 1 if the curve is invalid (non-finite data).
+ * ------------------------------------------------------------------------- */
+int ce_oracle_counts(const double *times, const double *mags, int64_t n,
+                     double period, double pdot, int32_t n_phase,
+                     int32_t n_mag, uint32_t *counts)
+{
+    if (n <= 0 || n_phase < 1 || n_mag < 1 || !times || !mags || !counts)
+        return ORACLE_EINVAL;
+    curve_prep cp;
+    if (prep_curve(times, mags, n, n_mag, &cp) != ORACLE_OK) {
+        free_prep(&cp);
+        return ORACLE_ENOMEM;
+    }
+    int rc = cp.valid ? ORACLE_OK : 1;
+    if (cp.valid)
+        trial_counts(&cp, 1.0 / period, 0.5 * pdot, 0, n_phase, n_mag, counts);
+    free_prep(&cp);
+    return rc;
+}
+
+static int check_offsets(const int64_t *off, int64_t n_curves)
+{
+    if (!off || n_curves < 1 || off[0] != 0)
+        return ORACLE_EINVAL;
+    for (int64_t c = 0; c < n_curves; ++c)
+        if (off[c + 1] <= off[c])
+            return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * The full grid search of Sec. 2.3: for every curve c, Pdot index q and
+ * period index p, H_c of Eq. (4) after the fold of Eq. (3).
+ *   times, mags      : [off[n_curves]] epochs and magnitudes, curve-major
+ *   off              : [n_curves + 1] curve offsets, off[0] = 0, increasing
+ *   periods, pdots   : [n_p], [n_pd] search grid (days, dimensionless)
+ *   out_ce           : [n_curves][n_pd][n_p] or NULL
+ *   best_flat        : [n_curves] first strict minimum, flat = q*n_p + p
+ *   best_ce          : [n_curves] H_c at best_flat
+ *   ponly            : nonzero => classic P-only fold, pdots ignored (n_pd
+ *                      is still the size of the q axis of out_ce)
+ *   n_threads        : OpenMP threads over (curve, q); <= 0 = runtime default
+ * The result does not depend on n_threads.
+ * ------------------------------------------------------------------------- */
+static int search_impl(const double *times, const double *mags,
+                       const int64_t *off, int64_t n_curves,
+                       const double *periods, int64_t n_p,
+                       const double *pdots, int64_t n_pd, int32_t n_phase,
+                       int32_t n_mag, double *out_ce, int64_t *best_flat,
+                       double *best_ce, int ponly, int32_t n_threads)
+{
+    if (!times || !mags || !periods || (!pdots && !ponly) || !best_flat ||
+        !best_ce || n_p < 1 || n_pd < 1 || n_phase < 1 || n_mag < 1)
+        return ORACLE_EINVAL;
+    if (check_offsets(off, n_curves) != ORACLE_OK)
+        return ORACLE_EINVAL;
+
+    curve_prep *cps = (curve_prep *)calloc((size_t)n_curves, sizeof(curve_prep));
+    if (!cps)
+        return ORACLE_ENOMEM;
+    int rc = ORACLE_OK;
+    for (int64_t c = 0; c < n_curves && rc == ORACLE_OK; ++c)
+        rc = prep_curve(times + off[c], mags + off[c], off[c + 1] - off[c],
+                        n_mag, &cps[c]);
+    /* A grid value that is not a finite positive period, or a non-finite
+     * Pdot, invalidates every curve. */
+    int grid_ok = 1;
+    for (int64_t p = 0; p < n_p; ++p)
+        if (!isfinite(periods[p]) || !(periods[p] > 0.0))
+            grid_ok = 0;
+    if (!ponly)
+        for (int64_t q = 0; q < n_pd; ++q)
+            if (!isfinite(pdots[q]))
+                grid_ok = 0;
+
+    /* per (curve, q) minimum, merged in flat order afterwards */
+    double *row_min = (double *)malloc((size_t)(n_curves * n_pd) * sizeof(double));
+    int64_t *row_arg = (int64_t *)malloc((size_t)(n_curves * n_pd) * sizeof(int64_t));
+    if (rc != ORACLE_OK || !row_min || !row_arg) {
+        rc = ORACLE_ENOMEM;
+        goto done;
+    }
+
+    int64_t n_rows = n_curves * n_pd;
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int alloc_fail = 0;
+#pragma omp parallel
+    {
+        uint32_t *counts = (uint32_t *)malloc((size_t)n_mag * (size_t)n_phase *
+                                              sizeof(uint32_t));
+        if (!counts) {
+#pragma omp atomic write
+            alloc_fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < n_rows; ++r) {
+            if (!counts)
+                continue;
+            int64_t c = r / n_pd, q = r % n_pd;
+            const curve_prep *cp = &cps[c];
+            double *row = out_ce ? out_ce + r * n_p : NULL;
+            double hmin = NAN;
+            int64_t pmin = -1;
+            if (!cp->valid || !grid_ok) {
+                if (row)
+                    for (int64_t p = 0; p < n_p; ++p)
+                        row[p] = NAN;
+            } else {
+                double half_pdot = ponly ? 0.0 : 0.5 * pdots[q];
+                for (int64_t p = 0; p < n_p; ++p) {
+                    double inv_p = 1.0 / periods[p];
+                    trial_counts(cp, inv_p, half_pdot, ponly, n_phase, n_mag,
+                                 counts);
+                    double h = ce_oracle_entropy(counts, n_mag, n_phase);
+                    if (row)
+                        row[p] = h;
+                    if (pmin < 0 || h < hmin) {
+                        hmin = h;
+                        pmin = p;
+                    }
+                }
+            }
+            row_min[r] = hmin;
+            row_arg[r] = pmin;
+        }
+        free(counts);
+    }
+    if (alloc_fail) {
+        rc = ORACLE_ENOMEM;
+        goto done;
+    }
+    for (int64_t c = 0; c < n_curves; ++c) {
+        best_flat[c] = -1;
+        best_ce[c] = NAN;
+        for (int64_t q = 0; q < n_pd; ++q) {
+            int64_t r = c * n_pd + q;
+            if (row_arg[r] < 0)
+                continue;
+            if (best_flat[c] < 0 || row_min[r] < best_ce[c]) {
+                best_ce[c] = row_min[r];
+                best_flat[c] = q * n_p + row_arg[r];
+            }
+        }
+    }
+done:
+    for (int64_t c = 0; c < n_curves; ++c)
+        free_prep(&cps[c]);
+    free(cps);
+    free(row_min);
+    free(row_arg);
+    return rc;
+}
+
+int ce_oracle_search(const double *times, const double *mags,
+                     const int64_t *off, int64_t n_curves,
+                     const double *periods, int64_t n_p, const double *pdots,
+                     int64_t n_pd, int32_t n_phase, int32_t n_mag,
+                     double *out_ce, int64_t *best_flat, double *best_ce,
+                     int32_t n_threads)
+{
+    return search_impl(times, mags, off, n_curves, periods, n_p, pdots, n_pd,
+                       n_phase, n_mag, out_ce, best_flat, best_ce, 0,
+                       n_threads);
+}
+
+/* Classic CE over periods only (Pdot absent from the fold); out_ce is
+ * [n_curves][n_p]. */
+int ce_oracle_search_ponly(const double *times, const double *mags,
+                           const int64_t *off, int64_t n_curves,
+                           const double *periods, int64_t n_p,
+                           int32_t n_phase, int32_t n_mag, double *out_ce,
+                           int64_t *best_flat, double *best_ce,
+                           int32_t n_threads)
+{
+    return search_impl(times, mags, off, n_curves, periods, n_p, NULL, 1,
+                       n_phase, n_mag, out_ce, best_flat, best_ce, 1,
+                       n_threads);
+}
+
+/* ---------------------------------------------------------------------------
+ * Selected trials only, for checks at sizes where the full cube is too slow:
+ * trial t is curve curve_ids[t] at flat index flat_ids[t] = q*n_p + p.
+ * out_ce[t] receives H_c; out_counts (optional) receives [n_mag][n_phase]
+ * counts per trial.  OpenMP over trials.
+ * ------------------------------------------------------------------------- */
+int ce_oracle_trials(const double *times, const double *mags,
+                     const int64_t *off, int64_t n_curves,
+                     const double *periods, int64_t n_p, const double *pdots,
+                     int64_t n_pd, int32_t n_phase, int32_t n_mag,
+                     const int64_t *curve_ids, const int64_t *flat_ids,
+                     int64_t n_trials, double *out_ce, uint32_t *out_counts,
+                     int32_t n_threads)
+{
+    if (!times || !mags || !periods || !pdots || !curve_ids || !flat_ids ||
+        !out_ce || n_p < 1 || n_pd < 1 || n_phase < 1 || n_mag < 1 ||
+        n_trials < 0)
+        return ORACLE_EINVAL;
+    if (check_offsets(off, n_curves) != ORACLE_OK)
+        return ORACLE_EINVAL;
+    for (int64_t t = 0; t < n_trials; ++t)
+        if (curve_ids[t] < 0 || curve_ids[t] >= n_curves || flat_ids[t] < 0 ||
+            flat_ids[t] >= n_p * n_pd)
+            return ORACLE_EINVAL;
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int fail = 0;
+    size_t cells = (size_t)n_mag * (size_t)n_phase;
+#pragma omp parallel
+    {
+        uint32_t *counts = (uint32_t *)malloc(cells * sizeof(uint32_t));
+        curve_prep cp;
+        int64_t cur = -1;
+        cp.dt = NULL;
+        cp.mbin = NULL;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t t = 0; t < n_trials; ++t) {
+            if (!counts) {
+#pragma omp atomic write
+                fail = 1;
+                continue;
+            }
+            int64_t c = curve_ids[t];
+            if (c != cur) {
+                free_prep(&cp);
+                if (prep_curve(times + off[c], mags + off[c],
+                               off[c + 1] - off[c], n_mag, &cp) != ORACLE_OK) {
+#pragma omp atomic write
+                    fail = 1;
+                    cur = -1;
+                    continue;
+                }
+                cur = c;
+            }
+            int64_t q = flat_ids[t] / n_p, p = flat_ids[t] % n_p;
+            int ok = cp.valid && isfinite(periods[p]) && periods[p] > 0.0 &&
+                     isfinite(pdots[q]);
+            if (!ok) {
+                out_ce[t] = NAN;
+                if (out_counts)
+                    memset(out_counts + (size_t)t * cells, 0,
+                           cells * sizeof(uint32_t));
+                continue;
+            }
+            trial_counts(&cp, 1.0 / periods[p], 0.5 * pdots[q], 0, n_phase,
+                         n_mag, counts);
+            out_ce[t] = ce_oracle_entropy(counts, n_mag, n_phase);
+            if (out_counts)
+                memcpy(out_counts + (size_t)t * cells, counts,
+                       cells * sizeof(uint32_t));
+        }
+        free_prep(&cp);
+        free(counts);
+    }
+    return fail ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
+int ce_oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
