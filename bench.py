@@ -1,0 +1,300 @@
+#!/usr/bin/env python3
+"""Benchmark: conditional-entropy (P, Pdot) search on one MI355X.
+
+One step = one whole search (grid set-up, per-curve preparation, the search
+kernel writing the full CE cube, per-curve minimum) over the batched workload:
+512 synthetic light curves x 600 epochs, 20,000 periods x 64 Pdots, 10 phase x
+5 magnitude bins (Katz et al. 2020, Sec. 2.3).  `value` is the FP64 path
+(bit-exact bins); the split-precision path (FP32 Pdot term and binning) is
+timed the same way and compared with it: recovered minima, CE differences and
+bin mismatches.  Inputs are resident in HBM before each timed region.  Prints
+one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("point-trials/sec (1 MI355X), split-FP32 vs FP64 at equal best-(P,Pdot); "
+          "% VALU peak")
+
+# MI355X published peaks (AMD): FP64 vector 78.6 TFLOP/s and FP32 vector
+# 157.3 TFLOP/s (FMA = 2; the FP32 figure counts packed dual-lane ops, which
+# this library does not use).  Any VALU instruction of a wave64 issues once per
+# 4 cycles per SIMD: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-instr/s.
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_VALU_TLANE = 256 * 64 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    1: "c1: 1 curve x 200 epochs, 2,000 P x 1 Pdot, 10x5 bins",
+    2: "c2: 512 curves x 600 epochs (3 yr nightly cadence, eclipses), "
+       "20,000 P x 64 Pdot, 10x5 bins",
+    4: "c4: 8,192 ragged curves (50-3,000 epochs), 10,000 P x 32 Pdot, 10x5 bins",
+    5: "c5: 64 curves x 5,000 epochs (10 yr, 2 filters), 100,000 P x 256 Pdot, "
+       "20x10 bins",
+}
+
+
+def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
+    """Algorithmic flops per point-trial (FMA = 2), the precision's own kind.
+
+    FP64: per point and trial y = fma(-Pdot/2, x^2, x) (2), y - floor(y) (1),
+    phase * n_phase (1); per point and period, shared by the n_pd trials,
+    x = dt * (1/P) (1) and x^2 (1).  Split: the per-trial part in FP32, the
+    same 4 flops.  Both: per trial the entropy sums, n_phase * (n_mag + 1)
+    additions, a subtraction and a division, spread over the curve's points.
+    """
+    return 4.0 + 2.0 / n_pd + (n_phase * (n_mag + 1) + 2) / mean_n
+
+
+def valu_instr_per_point_trial(precision, n_pd):
+    """VALU instructions the kernel's design needs per point-trial.
+
+    FP64: fma, fract, mul, cvt and the histogram address per point-trial;
+    x and x^2 per point-period.  Split: fma, fract, rounding fma and the
+    address per point-trial; x, x^2, frac(x) - shift and two conversions to
+    float per point-period."""
+    if precision == 0:
+        return 5.0 + 2.0 / n_pd
+    return 4.0 + 6.0 / n_pd
+
+
+def cpu_baseline(w, gpu_cube_rows, budget_s):
+    """Time the oracle (as it stands) on whole curves of the same workload
+    until about budget_s seconds of CPU work; compare its CE rows and minima
+    with the GPU's FP64 rows on the same curves."""
+    import numpy as np
+    import oracle
+
+    threads = oracle.max_threads()
+    done, spent, pt = 0, 0.0, 0
+    max_err, best_agree, best_checked = 0.0, 0, 0
+    per_curve = None
+    while done < w.n_curves:
+        if per_curve is not None and spent + 0.5 * per_curve > budget_s:
+            break
+        k = 1 if per_curve is None else max(1, min(w.n_curves - done,
+                                                  int((budget_s - spent) / per_curve)))
+        sub = w.subset(np.arange(done, done + k))
+        t0 = time.perf_counter()
+        oc, obf, obc = oracle.search(sub.times, sub.mags, sub.offsets, sub.periods,
+                                     sub.pdots, sub.n_phase, sub.n_mag, n_threads=threads)
+        spent += time.perf_counter() - t0
+        pt += sub.point_trials
+        per_curve = spent / (done + k)
+        g = gpu_cube_rows(done, done + k)
+        if g is not None:
+            max_err = max(max_err, float(np.abs(g - oc).max()))
+            best_agree += int(np.sum(g.reshape(k, -1).argmin(axis=1) == obf))
+            best_checked += k
+        done += k
+    return ({"value": pt / spent, "unit": "point-trials/s", "cores": threads,
+             "kind": "oracle",
+             "sample": f"{done} of {w.n_curves} curves, full {w.periods.size} x "
+                       f"{w.pdots.size} grid, {pt:.3g} point-trials in {spent:.1f} s"},
+            {"curves_compared": done, "max_abs_dH": max_err,
+             "argmin_equal": f"{best_agree}/{best_checked}"})
+
+
+def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube_on):
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
+                    precision=precision, trials_per_lane=tq, device=dev)
+    cube = plan.new_cube() if cube_on else None
+    best = plan.new_best()
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        plan.execute(*inputs, out_ce=cube, out_best=best, stream=stream)
+    torch.cuda.synchronize()
+    plan.set_timing(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(*inputs, out_ce=cube, out_best=best, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = plan.search_times_ms()
+    plan.set_timing(0)
+    return plan, cube, best, elapsed, float(np.mean(kernel_ms)) / 1e3
+
+
+def measured_traffic(config, precision):
+    """HBM bytes per search launch from the committed rocprofv3 counter
+    summary, or None when the kernel source has changed since it was taken
+    or the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_search_c{config}_traffic.json")
+    src = os.path.join(ROOT, "paper_2006_06866_amd", "csrc", "gce_kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    key = "k_search<fp64>" if precision == 0 else "k_search<split>"
+    return rec.get("per_launch_bytes", {}).get(key)
+
+
+def roofline(precision, w, kernel_s, config):
+    pt = w.point_trials
+    mean_n = float(w.lengths.mean())
+    fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag, mean_n)
+    achieved = fpp * pt / kernel_s / 1e12
+    peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
+    instr = valu_instr_per_point_trial(precision, w.pdots.size)
+    return {
+        "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": measured_traffic(config, precision),
+        "kernel": "k_search<%s>" % ("fp64" if precision == 0 else "split"),
+        "kernel_ms": kernel_s * 1e3, "flops_per_point_trial": fpp,
+        "valu_instr_per_point_trial": instr,
+        "valu_frac": instr * pt / kernel_s / 1e12 / PEAK_VALU_TLANE,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cube", action="store_true", help="minimum only (no CE cube)")
+    ap.add_argument("--trials-per-lane", type=int, default=0)
+    ap.add_argument("--no-split", action="store_true", help="skip the split leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU-baseline budget; 0 skips the oracle leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (the "
+                         "known-size kernel that scales HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.copy_calibration > 0:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
+                          "copies": 3}), flush=True)
+        return
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this search runs on one GPU only; multi-GPU runs are not "
+              "supported (each GPU would take its own share of the curves)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2006_06866_amd as gce
+    from paper_2006_06866_amd import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.make_config(args.config)
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    log(f"workload {WORKLOADS[args.config]}: {w.point_trials:.3g} point-trials")
+    inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
+    pt = w.point_trials
+    cube_on = not args.no_cube
+
+    plan64, cube64, best64, el64, k64 = timed_leg(
+        gce, torch, np, w, dev, inputs, 0, args.trials_per_lane, args.steps,
+        args.warmup, cube_on)
+    log(f"fp64: {el64 / args.steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
+    value = pt * args.steps / el64
+    bf64 = gce.best_fields(best64)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point-trials/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOADS[args.config],
+            "n_curves": w.n_curves, "points": int(w.offsets[-1]),
+            "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
+            "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
+            "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
+        },
+        "roofline": roofline(0, w, k64, args.config),
+    }
+    has = w.truth["inj_p"] >= 0
+    out["recovery_fp64"] = {
+        "curves_with_injection": int(has.sum()),
+        "injected_period_found": int(np.sum((bf64["period_index"] == w.truth["inj_p"]) & has)),
+        "injected_period_and_pdot_found": int(np.sum(
+            (bf64["period_index"] == w.truth["inj_p"]) &
+            (bf64["pdot_index"] == w.truth["inj_q"]) & has)),
+    }
+
+    if not args.no_split:
+        plan32, cube32, best32, el32, k32 = timed_leg(
+            gce, torch, np, w, dev, inputs, 1, args.trials_per_lane, args.steps,
+            args.warmup, cube_on)
+        log(f"split: {el32 / args.steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
+        bf32 = gce.best_fields(best32)
+        strict = int(np.sum(bf32["flat_index"] == bf64["flat_index"]))
+        split = {
+            "value": pt * args.steps / el32, "unit": "point-trials/s",
+            "ms_per_step": el32 / args.steps * 1e3,
+            "speedup_vs_fp64": el64 / el32,
+            "trials_per_lane": plan32.info()["trials_per_lane"],
+            "roofline": roofline(1, w, k32, args.config),
+            "best_equal_strict": f"{strict}/{w.n_curves}",
+        }
+        if cube_on:
+            # tolerant agreement: the FP64 CE at the split minimum is within
+            # 1e-5 of the FP64 minimum
+            flat64 = cube64.view(w.n_curves, -1)
+            h_at = flat64.gather(1, torch.from_numpy(bf32["flat_index"]).to(dev).view(-1, 1)).view(-1)
+            hmin = torch.from_numpy(bf64["ce_min"]).to(dev)
+            split["best_equal_tolerant_1e-5"] = (
+                f"{int(((h_at - hmin) <= 1e-5).sum().item())}/{w.n_curves}")
+            dh = (cube32.view(w.n_curves, -1).double() - flat64).abs()
+            split["max_abs_dH"] = float(dh.max().item())
+            split["frac_abs_dH_le_1e-5"] = float((dh <= 1e-5).double().mean().item())
+            del dh
+        # bin mismatches against the FP64 bins (which are bit-exact to the
+        # reference) on sampled trials
+        rng = np.random.default_rng(2006)
+        ci = rng.integers(0, w.n_curves, 4096)
+        fi = rng.integers(0, w.periods.size * w.pdots.size, 4096)
+        c64 = plan64.debug_counts(*inputs, ci, fi).long()
+        c32 = plan32.debug_counts(*inputs, ci, fi).long()
+        moved = float((c64 - c32).abs().sum().item()) / 2
+        split["count_mismatch_rate"] = moved / float(w.lengths[ci].sum())
+        split["count_mismatch_sample"] = "4096 random trials"
+        out["split"] = split
+        plan32.close()
+        del cube32
+
+    if args.cpu_seconds > 0:
+        def rows(a, b):
+            return None if cube64 is None else cube64[a:b].cpu().numpy()
+        cb, par = cpu_baseline(w, rows, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["parity"] = par
+    print(json.dumps(out), flush=True)
+    plan64.close()
+
+
+if __name__ == "__main__":
+    main()

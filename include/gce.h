@@ -1,0 +1,213 @@
+/*
+ * gce.h -- C ABI of the MI355X conditional-entropy period search.
+ *
+ * The library evaluates, for every light curve c, every period P_p and every
+ * period derivative Pdot_q of a search grid, the conditional entropy H_c of
+ * Katz et al. 2020 ("GPU-Accelerated Periodic Source Identification in
+ * Large-Scale Surveys: Measuring P and Pdot"), Sec. 2.3:
+ *
+ *   fold (Eq. (3)):    x = (t - t0) / P,   phi = frac(x - Pdot x^2 / 2)
+ *   histogram:         (magnitude bin, phase bin) counts, n_mag x n_phase
+ *   entropy (Eq. (4)): H_c = sum_ij p(m_i, phi_j) ln(p(phi_j) / p(m_i, phi_j))
+ *
+ * and the per-curve minimum of H_c over the grid (Sec. 2.3, Sec. 4: the
+ * minimum CE locates the period; batches keep their minimum and parameters).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: epochs and periods in days, Pdot dimensionless.
+ *  - t0 is the earliest epoch of each curve.  Magnitudes are normalised per
+ *    curve onto [0, 1] by their minimum and maximum and cut into n_mag equal
+ *    bins (the maximum falls in the last bin; a constant curve has one bin).
+ *  - Fold arithmetic is IEEE binary64 in this order: invP = 1.0 / P
+ *    (correctly rounded), x = dt * invP, x2 = x * x,
+ *    y = fma(-(0.5 * Pdot), x2, x), phi = y - floor(y),
+ *    phase bin = min((int)(phi * n_phase), n_phase - 1).  The FP64 path
+ *    reproduces these bins bit for bit.
+ *  - Curves are ragged: epochs of curve c occupy [offsets[c], offsets[c+1])
+ *    of the concatenated `times` / `mags` arrays.
+ *  - The CE cube is row-major [curve][pdot][period] (period fastest); the
+ *    flat index of a trial is q * n_periods + p.  The per-curve minimum is
+ *    the lowest flat index among the trials with the smallest H_c.
+ *  - Pointers are device pointers (hipMalloc or equivalent) unless marked
+ *    HOST.  The caller owns every buffer; the library keeps no pointer to
+ *    caller memory after the work it enqueued has completed.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work and return; results are valid once the stream has been synchronised.
+ *  - Errors: every entry point returns GCE_OK (0) or a negative GCE_E* code;
+ *    gce_status_string() describes the last error of the calling thread.
+ *    Argument errors are detected on the host before anything is enqueued.
+ *    Bad data values (non-finite epochs or magnitudes, a period outside
+ *    [1e-12, 1e12] days or NaN, |Pdot| > 1 or NaN, epochs of one curve
+ *    spanning more than 1e12 days) cannot be reported synchronously: the affected
+ *    curves (all curves for a bad grid) get flat_index = -1, ce_min = NaN and
+ *    NaN CE values.
+ *  - Limits: 1 <= n_phase_bins <= 128, 1 <= n_mag_bins <= 255,
+ *    1 <= points per curve <= 65535 (counts are 16-bit).
+ */
+#ifndef GCE_H
+#define GCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCE_OK 0
+#define GCE_EINVAL (-1)        /* bad argument (pointer, count, size, offsets) */
+#define GCE_ENOMEM (-2)        /* device or host allocation failed */
+#define GCE_EHIP (-3)          /* a HIP runtime call failed */
+#define GCE_EWORKSPACE (-4)    /* caller workspace too small */
+#define GCE_ENODEV (-5)        /* no usable gfx950 device */
+#define GCE_EUNSUPPORTED (-6)  /* option combination not supported */
+
+/* Precision of the fold / entropy arithmetic. */
+#define GCE_PRECISION_FP64 0        /* bit-exact bins, FP64 entropy */
+#define GCE_PRECISION_SPLIT_FP32 1  /* FP32 Pdot term and binning, FP64 entropy;
+                                       approximate bins, FP32 CE cube */
+
+/* Per-curve result (40 bytes). */
+typedef struct {
+    int64_t flat_index;   /* q * n_periods + p of the minimum; -1 if invalid */
+    int32_t period_index; /* p; -1 if invalid */
+    int32_t pdot_index;   /* q; -1 if invalid */
+    double ce_min;        /* H_c at flat_index; NaN if invalid */
+    double ce_mean;       /* mean of H_c over the grid (Eq. (5)); NaN unless
+                             statistics were requested */
+    double ce_std;        /* population std of H_c over the grid; NaN unless
+                             statistics were requested */
+} gce_best_t;
+
+/*
+ * gce_search -- one-call FP64 search (Sec. 2.3, Eqs. (3)-(4)).
+ *
+ *  times, mags     : device, [offsets[n_curves]] doubles, curve-major.
+ *  curve_offsets   : HOST, [n_curves + 1], offsets[0] = 0, strictly
+ *                    increasing, each curve 1..65535 epochs.
+ *  periods         : device, [n_periods] doubles (days), any order.
+ *  pdots           : device, [n_pdots] doubles, any order.
+ *  n_phase_bins, n_mag_bins : histogram shape.
+ *  out_ce          : device, [n_curves][n_pdots][n_periods] doubles, or NULL
+ *                    to skip the cube (minimum only).
+ *  out_best        : device, [n_curves] gce_best_t.
+ *  stream          : hipStream_t.
+ *
+ * Allocates (once, cached per device and shape) a workspace; not safe to
+ * call during stream capture unless an identical call has already run on
+ * this device.  Returns GCE_OK or a negative GCE_E* code.
+ */
+int gce_search(const double *times, const double *mags,
+               const int64_t *curve_offsets, int64_t n_curves,
+               const double *periods, int64_t n_periods, const double *pdots,
+               int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
+               double *out_ce, gce_best_t *out_best, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Plans: validation, scheduling and allocation once; execution many times.
+ * gce_plan_execute allocates nothing and copies nothing between host and
+ * device, so it may be captured into a HIP graph.
+ * ------------------------------------------------------------------------ */
+typedef struct gce_plan_s *gce_plan_t;
+
+typedef struct {
+    int32_t precision;       /* GCE_PRECISION_* */
+    int32_t trials_per_lane; /* Pdot trials per lane: 0 = automatic, else
+                                1, 2, 4 or 8 */
+    int32_t statistics;      /* nonzero: fill ce_mean / ce_std (Eq. (5)) */
+    int32_t reserved;
+} gce_opts;
+
+/*
+ * gce_plan_create -- validate the shape and the HOST offsets, build the
+ * schedule (curves ordered by decreasing length), allocate the device
+ * workspace and upload the per-curve metadata.  Synchronous.
+ *  plan          : out, the new plan.
+ *  curve_offsets : HOST, [n_curves + 1] as for gce_search (copied).
+ *  opts          : may be NULL (FP64, automatic tiling, no statistics).
+ *  device        : HIP device ordinal the plan runs on.
+ */
+int gce_plan_create(gce_plan_t *plan, const int64_t *curve_offsets,
+                    int64_t n_curves, int64_t n_periods, int64_t n_pdots,
+                    int32_t n_phase_bins, int32_t n_mag_bins,
+                    const gce_opts *opts, int32_t device);
+
+/*
+ * gce_plan_execute -- enqueue the whole search on `stream`: grid check,
+ * per-curve preparation (t0, magnitude bins, points grouped by magnitude
+ * bin), the search kernel, and the per-curve minimum.
+ *  times, mags : device, laid out as the plan's offsets describe.
+ *  periods     : device, [n_periods].  pdots : device, [n_pdots].
+ *  out_ce      : device cube [n_curves][n_pdots][n_periods] or NULL.
+ *                FP64 plans write doubles; SPLIT_FP32 plans write floats
+ *                through the same pointer (cast by the caller).
+ *  out_best    : device, [n_curves].
+ * Calls that overlap on one plan race on its workspace.
+ */
+int gce_plan_execute(gce_plan_t plan, const double *times, const double *mags,
+                     const double *periods, const double *pdots,
+                     void *out_ce, gce_best_t *out_best, void *stream);
+
+/*
+ * gce_plan_debug_counts -- test hook: the [n_mag][n_phase] histogram of
+ * selected trials, binned by the same device code as the search.
+ *  trial_curve, trial_flat : device, [n_trials] int64 (curve, flat index).
+ *  out_counts  : device, [n_trials][n_mag][n_phase] uint32.
+ * Out-of-range trial ids give all-zero histograms.
+ */
+int gce_plan_debug_counts(gce_plan_t plan, const double *times,
+                          const double *mags, const double *periods,
+                          const double *pdots, const int64_t *trial_curve,
+                          const int64_t *trial_flat, int64_t n_trials,
+                          uint32_t *out_counts, void *stream);
+
+/*
+ * gce_plan_set_timing -- measurement hook.  With capacity > 0 the plan keeps
+ * a ring of `capacity` HIP event pairs and records one pair around the
+ * search kernel of every later gce_plan_execute, on that call's stream
+ * (leave it off under graph capture).  capacity = 0 disables it and frees
+ * the events.  Returns GCE_EINVAL for capacity < 0 or > 65536.
+ */
+int gce_plan_set_timing(gce_plan_t plan, int32_t capacity);
+
+/*
+ * gce_plan_search_times -- search-kernel durations in milliseconds of the
+ * most recent min(executes since enabling, capacity) executes, oldest first.
+ * Waits for the recorded events.  out_ms: HOST, room for max values;
+ * *n_out receives the number written.
+ */
+int gce_plan_search_times(gce_plan_t plan, float *out_ms, int32_t max,
+                          int32_t *n_out);
+
+/* What a plan chose: tiling and resources of its search kernel. */
+typedef struct {
+    int32_t precision;          /* GCE_PRECISION_* */
+    int32_t trials_per_lane;    /* Pdot trials per lane actually used */
+    int32_t lds_bytes_per_wave; /* histogram LDS of one search wave */
+    int32_t reserved;
+    int64_t work_units;         /* waves of one search launch */
+    int64_t workspace_bytes;    /* device workspace held by the plan */
+} gce_plan_info_t;
+
+/* Fill *info for the plan.  Returns GCE_EINVAL for NULL arguments. */
+int gce_plan_get_info(gce_plan_t plan, gce_plan_info_t *info);
+
+/* Bytes of device workspace the plan holds. */
+size_t gce_plan_workspace_bytes(gce_plan_t plan);
+
+/* Release the plan and its workspace (synchronises the device first). */
+int gce_plan_destroy(gce_plan_t plan);
+
+/* Human-readable text for a status code; for GCE_EHIP it includes the HIP
+ * error of the calling thread's last failing call. */
+const char *gce_status_string(int status);
+
+/* Library version string. */
+const char *gce_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCE_H */

@@ -1,0 +1,502 @@
+// gce_api.cpp -- host side of the C ABI declared in include/gce.h:
+// argument validation, scheduling, workspace, plan cache and error text.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gce.h"
+#include "gce_internal.h"
+
+using gce::DevPlan;
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local char g_status_buf[512];
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(GCE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int check_device(int dev)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(GCE_ENODEV, "no HIP device available");
+    if (dev < 0 || dev >= count)
+        return fail(GCE_ENODEV, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(GCE_ENODEV, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GCE_ENODEV, std::string("device is ") + prop.gcnArchName +
+                                    ", the library is built for gfx950 only");
+    return GCE_OK;
+}
+
+int choose_tq(int precision, int n_phase, int64_t n_pd, int requested)
+{
+    if (requested > 0) return requested;
+    // Pdot trials per lane: more trials share each point's x and x^2, but
+    // every trial adds histogram LDS and registers.  Measured on MI355X
+    // (512 x 600 epochs, 20,000 x 64 grid, 10 phase bins): both kernels are
+    // fastest at 8 (FP64 8/4/2: 60/64/73 ms; split 8/4: 51/54 ms).
+    (void)precision;
+    int tq = 8;
+    while (tq > 1 && (tq >= 2 * n_pd ||
+                      !gce::search_variant_exists(precision, n_phase, tq) ||
+                      gce::search_lds_bytes(precision, n_phase, tq) > 24 * 1024))
+        tq /= 2;
+    return tq;
+}
+
+}  // namespace
+
+struct gce_plan_s {
+    int device = 0;
+    gce_opts opts{};
+    DevPlan dp{};
+    int64_t total_points = 0;
+    std::vector<int64_t> off_host;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint64_t key_hash = 0;
+    // search-kernel timing ring (gce_plan_set_timing)
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    int64_t n_timed = 0;
+};
+
+namespace {
+
+uint64_t hash_offsets(const int64_t *off, int64_t n)
+{
+    uint64_t h = 1469598103934665603ull;   // FNV-1a over the offset words
+    for (int64_t i = 0; i <= n; ++i) {
+        uint64_t v = (uint64_t)off[i];
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    }
+    return h;
+}
+
+int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
+                   int64_t n_pd, int32_t n_phase, int32_t n_mag,
+                   int32_t *max_n_out)
+{
+    if (!off) return fail(GCE_EINVAL, "curve_offsets is NULL");
+    if (n_curves < 1) return fail(GCE_EINVAL, "n_curves must be >= 1");
+    if (n_p < 1 || n_pd < 1) return fail(GCE_EINVAL, "grid sizes must be >= 1");
+    if (n_phase < 1 || n_phase > gce::kMaxPhaseBins)
+        return fail(GCE_EINVAL, "n_phase_bins out of range [1, 128]");
+    if (n_mag < 1 || n_mag > gce::kMaxMagBins)
+        return fail(GCE_EINVAL, "n_mag_bins out of range [1, 255]");
+    if (off[0] != 0) return fail(GCE_EINVAL, "curve_offsets[0] must be 0");
+    int64_t max_n = 0;
+    for (int64_t c = 0; c < n_curves; ++c) {
+        const int64_t n = off[c + 1] - off[c];
+        if (n < 1) return fail(GCE_EINVAL, "curve with no epochs (offsets not increasing)");
+        if (n > gce::kMaxPoints) return fail(GCE_EINVAL, "curve longer than 65535 epochs");
+        max_n = std::max(max_n, n);
+    }
+    // kernel grids are 1-D with at most 2^31 - 1 work units
+    const int64_t n_ptiles = (n_p + gce::kWave - 1) / gce::kWave;
+    if (n_ptiles > (int64_t)1 << 30 || n_pd > (int64_t)1 << 30)
+        return fail(GCE_EINVAL, "grid too large");
+    *max_n_out = (int32_t)max_n;
+    return GCE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gce_version(void) { return "gce-mi355x 0.1.0 (gfx950)"; }
+
+const char *gce_status_string(int status)
+{
+    const char *base = "unknown status";
+    switch (status) {
+    case GCE_OK: base = "success"; break;
+    case GCE_EINVAL: base = "invalid argument"; break;
+    case GCE_ENOMEM: base = "out of memory"; break;
+    case GCE_EHIP: base = "HIP runtime error"; break;
+    case GCE_EWORKSPACE: base = "workspace too small"; break;
+    case GCE_ENODEV: base = "no usable gfx950 device"; break;
+    case GCE_EUNSUPPORTED: base = "unsupported option"; break;
+    default: break;
+    }
+    if (status != GCE_OK && !g_last_error.empty())
+        std::snprintf(g_status_buf, sizeof(g_status_buf), "%s: %s", base,
+                      g_last_error.c_str());
+    else
+        std::snprintf(g_status_buf, sizeof(g_status_buf), "%s", base);
+    return g_status_buf;
+}
+
+int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
+                    int64_t n_curves, int64_t n_periods, int64_t n_pdots,
+                    int32_t n_phase_bins, int32_t n_mag_bins,
+                    const gce_opts *opts, int32_t device)
+{
+    if (!plan_out) return fail(GCE_EINVAL, "plan pointer is NULL");
+    *plan_out = nullptr;
+    int32_t max_n = 0;
+    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
+                            n_phase_bins, n_mag_bins, &max_n);
+    if (rc != GCE_OK) return rc;
+    gce_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != GCE_PRECISION_FP64 && o.precision != GCE_PRECISION_SPLIT_FP32)
+        return fail(GCE_EINVAL, "unknown precision");
+    if (o.trials_per_lane != 0 && o.trials_per_lane != 1 && o.trials_per_lane != 2 &&
+        o.trials_per_lane != 4 && o.trials_per_lane != 8)
+        return fail(GCE_EINVAL, "trials_per_lane must be 0, 1, 2, 4 or 8");
+    if (o.statistics)
+        return fail(GCE_EUNSUPPORTED, "statistics are not built in this library");
+    const int tq = choose_tq(o.precision, n_phase_bins, n_pdots, o.trials_per_lane);
+    if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
+        return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
+    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq) > 64 * 1024)
+        return fail(GCE_EUNSUPPORTED, "histograms exceed 64 KiB of LDS: lower trials_per_lane");
+
+    rc = check_device(device);
+    if (rc != GCE_OK) return rc;
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
+
+    gce_plan_s *pl = new (std::nothrow) gce_plan_s();
+    if (!pl) return fail(GCE_ENOMEM, "host allocation failed");
+    pl->device = device;
+    pl->opts = o;
+    pl->off_host.assign(curve_offsets, curve_offsets + n_curves + 1);
+    pl->total_points = curve_offsets[n_curves];
+    pl->key_hash = hash_offsets(curve_offsets, n_curves);
+
+    DevPlan &dp = pl->dp;
+    dp.n_curves = n_curves;
+    dp.n_p = n_periods;
+    dp.n_pd = n_pdots;
+    dp.n_phase = n_phase_bins;
+    dp.n_mag = n_mag_bins;
+    dp.tq = tq;
+    dp.n_qgroups = (int32_t)((n_pdots + tq - 1) / tq);
+    dp.n_ptiles = (n_periods + gce::kWave - 1) / gce::kWave;
+    dp.units_per_curve = (int64_t)dp.n_qgroups * dp.n_ptiles;
+    dp.n_units = n_curves * dp.units_per_curve;
+    dp.max_n = max_n;
+    dp.precision = o.precision;
+    dp.statistics = o.statistics;
+    if (dp.n_units > 0x7fffffffll) {
+        delete pl;
+        return fail(GCE_EINVAL, "too many work units for one launch");
+    }
+
+    // schedule: longest curves first (stable), so ragged batches drain evenly
+    std::vector<int32_t> order((size_t)n_curves);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (curve_offsets[a + 1] - curve_offsets[a]) >
+               (curve_offsets[b + 1] - curve_offsets[b]);
+    });
+
+    // workspace layout
+    const size_t A = 256;
+    size_t sz = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = sz;
+        sz = align_up(sz + bytes, A);
+        return at;
+    };
+    const size_t o_off = take(sizeof(int64_t) * (size_t)(n_curves + 1));
+    const size_t o_order = take(sizeof(int32_t) * (size_t)n_curves);
+    const size_t o_lut = take(sizeof(double) * (size_t)(max_n + 1));
+    const size_t o_lut32 = take(sizeof(float) * (size_t)(max_n + 1));
+    const size_t o_dt = take(sizeof(double) * (size_t)pl->total_points);
+    const size_t o_seg = take(sizeof(int32_t) * (size_t)n_curves * (size_t)(n_mag_bins + 1));
+    const size_t o_cok = take(sizeof(int32_t) * (size_t)n_curves);
+    const size_t o_gok = take(sizeof(int32_t));
+    const size_t o_invp = take(sizeof(double) * (size_t)n_periods);
+    const size_t o_hpd = take(sizeof(double) * (size_t)n_pdots);
+    const size_t o_hpd32 = take(sizeof(float) * (size_t)n_pdots);
+    const size_t o_part = take(sizeof(gce::Partial) * (size_t)dp.n_units);
+    pl->ws_bytes = sz;
+
+    hipError_t e = hipMalloc(&pl->ws, sz);
+    if (e != hipSuccess) {
+        delete pl;
+        (void)hipGetLastError();
+        return fail(GCE_ENOMEM, "hipMalloc of the workspace failed");
+    }
+    char *w = static_cast<char *>(pl->ws);
+    dp.off = reinterpret_cast<const int64_t *>(w + o_off);
+    dp.order = reinterpret_cast<const int32_t *>(w + o_order);
+    dp.lut = reinterpret_cast<const double *>(w + o_lut);
+    dp.lut32 = reinterpret_cast<const float *>(w + o_lut32);
+    dp.dt_sorted = reinterpret_cast<double *>(w + o_dt);
+    dp.seg = reinterpret_cast<int32_t *>(w + o_seg);
+    dp.curve_ok = reinterpret_cast<int32_t *>(w + o_cok);
+    dp.grid_ok = reinterpret_cast<int32_t *>(w + o_gok);
+    dp.inv_p = reinterpret_cast<double *>(w + o_invp);
+    dp.half_pd = reinterpret_cast<double *>(w + o_hpd);
+    dp.half_pd32 = reinterpret_cast<float *>(w + o_hpd32);
+    dp.partials = reinterpret_cast<gce::Partial *>(w + o_part);
+    dp.stats = nullptr;
+
+    e = hipMemcpy(const_cast<int64_t *>(dp.off), curve_offsets,
+                  sizeof(int64_t) * (size_t)(n_curves + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(const_cast<int32_t *>(dp.order), order.data(),
+                      sizeof(int32_t) * (size_t)n_curves, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = gce::launch_lut(dp, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        int r = fail_hip(e, "plan set-up");
+        (void)hipFree(pl->ws);
+        delete pl;
+        return r;
+    }
+    *plan_out = pl;
+    return GCE_OK;
+}
+
+int gce_plan_execute(gce_plan_t pl, const double *times, const double *mags,
+                     const double *periods, const double *pdots, void *out_ce,
+                     gce_best_t *out_best, void *stream)
+{
+    if (!pl) return fail(GCE_EINVAL, "plan is NULL");
+    if (!times || !mags || !periods || !pdots || !out_best)
+        return fail(GCE_EINVAL, "NULL input or output pointer");
+    DeviceGuard guard(pl->device);
+    if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const DevPlan &dp = pl->dp;
+    hipError_t e = gce::launch_grid_setup(dp, periods, pdots, s);
+    if (e != hipSuccess) return fail_hip(e, "grid set-up launch");
+    e = gce::launch_prepass(dp, times, mags, s);
+    if (e != hipSuccess) return fail_hip(e, "prepass launch");
+    const bool timed = !pl->ev_start.empty();
+    const size_t slot = timed ? (size_t)(pl->n_timed % (int64_t)pl->ev_start.size()) : 0;
+    if (timed && (e = hipEventRecord(pl->ev_start[slot], s)) != hipSuccess)
+        return fail_hip(e, "timing event");
+    e = gce::launch_search(dp, out_ce, s);
+    if (e != hipSuccess) return fail_hip(e, "search launch");
+    if (timed) {
+        if ((e = hipEventRecord(pl->ev_stop[slot], s)) != hipSuccess)
+            return fail_hip(e, "timing event");
+        ++pl->n_timed;
+    }
+    e = gce::launch_epilogue(dp, out_best, s);
+    if (e != hipSuccess) return fail_hip(e, "epilogue launch");
+    return GCE_OK;
+}
+
+int gce_plan_debug_counts(gce_plan_t pl, const double *times,
+                          const double *mags, const double *periods,
+                          const double *pdots, const int64_t *trial_curve,
+                          const int64_t *trial_flat, int64_t n_trials,
+                          uint32_t *out_counts, void *stream)
+{
+    if (!pl) return fail(GCE_EINVAL, "plan is NULL");
+    if (n_trials < 0) return fail(GCE_EINVAL, "n_trials < 0");
+    if (!times || !mags || !periods || !pdots ||
+        (n_trials > 0 && (!trial_curve || !trial_flat || !out_counts)))
+        return fail(GCE_EINVAL, "NULL pointer");
+    if (n_trials > ((int64_t)1 << 31) - 64) return fail(GCE_EINVAL, "too many trials");
+    DeviceGuard guard(pl->device);
+    if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const DevPlan &dp = pl->dp;
+    hipError_t e = gce::launch_grid_setup(dp, periods, pdots, s);
+    if (e == hipSuccess) e = gce::launch_prepass(dp, times, mags, s);
+    if (e == hipSuccess)
+        e = gce::launch_debug_counts(dp, trial_curve, trial_flat, n_trials, out_counts, s);
+    if (e != hipSuccess) return fail_hip(e, "debug counts launch");
+    return GCE_OK;
+}
+
+size_t gce_plan_workspace_bytes(gce_plan_t pl) { return pl ? pl->ws_bytes : 0; }
+
+int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
+{
+    if (!pl || !info) return fail(GCE_EINVAL, "NULL argument");
+    info->precision = pl->dp.precision;
+    info->trials_per_lane = pl->dp.tq;
+    info->lds_bytes_per_wave =
+        (int32_t)gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq);
+    info->reserved = 0;
+    info->work_units = pl->dp.n_units;
+    info->workspace_bytes = (int64_t)pl->ws_bytes;
+    return GCE_OK;
+}
+
+static void free_timing(gce_plan_s *pl)
+{
+    for (hipEvent_t ev : pl->ev_start) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : pl->ev_stop) (void)hipEventDestroy(ev);
+    pl->ev_start.clear();
+    pl->ev_stop.clear();
+    pl->n_timed = 0;
+}
+
+int gce_plan_set_timing(gce_plan_t pl, int32_t capacity)
+{
+    if (!pl) return fail(GCE_EINVAL, "plan is NULL");
+    if (capacity < 0 || capacity > 65536) return fail(GCE_EINVAL, "capacity out of range");
+    DeviceGuard guard(pl->device);
+    if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
+    (void)hipDeviceSynchronize();
+    free_timing(pl);
+    for (int32_t i = 0; i < capacity; ++i) {
+        hipEvent_t a = nullptr, b = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            free_timing(pl);
+            return fail_hip(e, "hipEventCreate");
+        }
+        pl->ev_start.push_back(a);
+        pl->ev_stop.push_back(b);
+    }
+    return GCE_OK;
+}
+
+int gce_plan_search_times(gce_plan_t pl, float *out_ms, int32_t max, int32_t *n_out)
+{
+    if (!pl || !n_out || max < 0 || (max > 0 && !out_ms))
+        return fail(GCE_EINVAL, "bad argument");
+    *n_out = 0;
+    const int64_t cap = (int64_t)pl->ev_start.size();
+    if (cap == 0) return GCE_OK;
+    const int64_t avail = std::min<int64_t>(pl->n_timed, cap);
+    const int64_t n = std::min<int64_t>(avail, max);
+    DeviceGuard guard(pl->device);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = pl->n_timed - n + i;   // oldest of the last n first
+        const size_t slot = (size_t)(k % cap);
+        hipError_t e = hipEventSynchronize(pl->ev_stop[slot]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pl->ev_start[slot], pl->ev_stop[slot]);
+        if (e != hipSuccess) return fail_hip(e, "timing read-out");
+        out_ms[i] = ms;
+    }
+    *n_out = (int32_t)n;
+    return GCE_OK;
+}
+
+int gce_plan_destroy(gce_plan_t pl)
+{
+    if (!pl) return GCE_OK;
+    int rc = GCE_OK;
+    {
+        DeviceGuard guard(pl->device);
+        hipError_t e = hipDeviceSynchronize();
+        free_timing(pl);
+        if (e == hipSuccess) e = hipFree(pl->ws);
+        if (e != hipSuccess) rc = fail_hip(e, "plan destroy");
+    }
+    delete pl;
+    return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// gce_search: a small cache of plans keyed by device and shape
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CacheEntry {
+    int device;
+    int64_t n_curves, n_p, n_pd;
+    int32_t n_phase, n_mag;
+    uint64_t hash;
+    gce_plan_t plan;
+};
+
+std::mutex g_cache_mu;
+std::list<CacheEntry> g_cache;   // most recent first
+constexpr size_t kCacheMax = 4;
+
+}  // namespace
+
+extern "C" int gce_search(const double *times, const double *mags,
+                          const int64_t *curve_offsets, int64_t n_curves,
+                          const double *periods, int64_t n_periods,
+                          const double *pdots, int64_t n_pdots,
+                          int32_t n_phase_bins, int32_t n_mag_bins,
+                          double *out_ce, gce_best_t *out_best, void *stream)
+{
+    int32_t max_n = 0;
+    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
+                            n_phase_bins, n_mag_bins, &max_n);
+    if (rc != GCE_OK) return rc;
+    if (!times || !mags || !periods || !pdots || !out_best)
+        return fail(GCE_EINVAL, "NULL input or output pointer");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GCE_ENODEV, "hipGetDevice failed");
+    const uint64_t h = hash_offsets(curve_offsets, n_curves);
+
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    gce_plan_t plan = nullptr;
+    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+        if (it->device == dev && it->n_curves == n_curves && it->n_p == n_periods &&
+            it->n_pd == n_pdots && it->n_phase == n_phase_bins &&
+            it->n_mag == n_mag_bins && it->hash == h &&
+            std::equal(curve_offsets, curve_offsets + n_curves + 1,
+                       it->plan->off_host.begin())) {
+            plan = it->plan;
+            g_cache.splice(g_cache.begin(), g_cache, it);
+            break;
+        }
+    }
+    if (!plan) {
+        rc = gce_plan_create(&plan, curve_offsets, n_curves, n_periods, n_pdots,
+                             n_phase_bins, n_mag_bins, nullptr, dev);
+        if (rc != GCE_OK) return rc;
+        g_cache.push_front(CacheEntry{dev, n_curves, n_periods, n_pdots,
+                                      n_phase_bins, n_mag_bins, h, plan});
+        while (g_cache.size() > kCacheMax) {
+            gce_plan_destroy(g_cache.back().plan);
+            g_cache.pop_back();
+        }
+    }
+    return gce_plan_execute(plan, times, mags, periods, pdots, out_ce, out_best,
+                            stream);
+}

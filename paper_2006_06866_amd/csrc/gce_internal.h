@@ -1,0 +1,82 @@
+// gce_internal.h -- shapes, workspace views and kernel launchers shared by
+// the host API (gce_api.cpp) and the HIP kernels (gce_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "gce.h"
+
+namespace gce {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxPoints = 65535;    // 16-bit histogram counters
+constexpr int kMaxMagBins = 255;
+constexpr int kMaxPhaseBins = 128;   // LDS budget of the generic kernel
+constexpr double kMaxSpanDays = 1e12;
+constexpr double kMinPeriod = 1e-12;
+constexpr double kMaxPeriod = 1e12;
+constexpr double kMaxAbsPdot = 1.0;
+
+// Minimum of one work unit: smallest H_c and its flat index (-1: none).
+struct Partial {
+    double h;
+    int64_t flat;
+};
+
+// Everything a kernel needs: the shape, the schedule and views into the
+// plan's device workspace.  Passed to kernels by value.
+struct DevPlan {
+    int64_t n_curves;
+    int64_t n_p;
+    int64_t n_pd;
+    int32_t n_phase;
+    int32_t n_mag;
+    int32_t tq;               // Pdot trials per lane
+    int32_t n_qgroups;        // ceil(n_pd / tq)
+    int64_t n_ptiles;         // ceil(n_p / 64)
+    int64_t units_per_curve;  // n_qgroups * n_ptiles
+    int64_t n_units;          // n_curves * units_per_curve
+    int32_t max_n;            // longest curve
+    int32_t precision;
+    int32_t statistics;
+
+    // plan-time metadata
+    const int64_t *off;       // [n_curves + 1] curve offsets
+    const int32_t *order;     // [n_curves] schedule rank -> curve
+    const double *lut;        // [max_n + 1] c * ln(c)
+    const float *lut32;       // [max_n + 1] c * ln(c), float
+
+    // per-execution scratch
+    double *dt_sorted;        // [total] t - t0, grouped by magnitude bin
+    int32_t *seg;             // [n_curves][n_mag + 1] segment starts
+    int32_t *curve_ok;        // [n_curves]
+    int32_t *grid_ok;         // [1]
+    double *inv_p;            // [n_p] 1 / P
+    double *half_pd;          // [n_pd] Pdot / 2
+    float *half_pd32;         // [n_pd] Pdot / 2 rounded to float (split path)
+    Partial *partials;        // [n_units]
+    double *stats;            // [n_units][2] sum and sum of squares (or NULL)
+};
+
+// Kernel launchers (gce_kernels.hip).  Each returns the launch status.
+hipError_t launch_lut(const DevPlan &dp, hipStream_t s);
+hipError_t launch_grid_setup(const DevPlan &dp, const double *periods,
+                             const double *pdots, hipStream_t s);
+hipError_t launch_prepass(const DevPlan &dp, const double *times,
+                          const double *mags, hipStream_t s);
+hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s);
+hipError_t launch_epilogue(const DevPlan &dp, gce_best_t *out_best,
+                           hipStream_t s);
+hipError_t launch_debug_counts(const DevPlan &dp, const int64_t *trial_curve,
+                               const int64_t *trial_flat, int64_t n_trials,
+                               uint32_t *out_counts, hipStream_t s);
+
+// Search-kernel variants compiled into the library.
+bool search_variant_exists(int precision, int n_phase, int tq);
+// Bytes of LDS one search wave uses.
+size_t search_lds_bytes(int precision, int n_phase, int tq);
+
+}  // namespace gce

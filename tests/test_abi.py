@@ -1,0 +1,102 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects bad arguments on the host (no GPU compute here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2006_06866_amd as gce
+from paper_2006_06866_amd import build as gbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gce.h")
+
+
+def _ensure_built():
+    if not os.path.exists(gce.LIB_PATH):
+        gbuild.build()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*[\s\*]+([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith("gce_")))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("gce_search", "gce_plan_create", "gce_plan_execute",
+                     "gce_plan_debug_counts", "gce_plan_destroy",
+                     "gce_plan_workspace_bytes", "gce_status_string", "gce_version"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    _ensure_built()
+    lib = ctypes.CDLL(gce.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    _ensure_built()
+    L = gce.lib()
+    assert b"gfx950" in L.gce_version()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert len(L.gce_status_string(code)) > 0
+
+
+@pytest.mark.parametrize("offsets,n_p,n_pd,n_phase,n_mag", [
+    ([0, 5, 3], 10, 2, 10, 5),          # decreasing offsets
+    ([0, 5, 5], 10, 2, 10, 5),          # empty curve
+    ([1, 5, 9], 10, 2, 10, 5),          # offsets[0] != 0
+    ([0, 70000], 10, 2, 10, 5),         # curve longer than 65535
+    ([0, 5], 0, 2, 10, 5),              # no periods
+    ([0, 5], 10, 0, 10, 5),             # no pdots
+    ([0, 5], 10, 2, 0, 5),              # no phase bins
+    ([0, 5], 10, 2, 129, 5),            # too many phase bins
+    ([0, 5], 10, 2, 10, 0),             # no magnitude bins
+    ([0, 5], 10, 2, 10, 256),           # too many magnitude bins
+])
+def test_bad_shapes_rejected_on_host(offsets, n_p, n_pd, n_phase, n_mag):
+    _ensure_built()
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array(offsets), n_p, n_pd, n_phase, n_mag, device="cuda:0")
+    assert ei.value.status == -1
+
+
+def test_bad_options_rejected_on_host():
+    _ensure_built()
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array([0, 5]), 10, 2, 10, 5, trials_per_lane=16, device="cuda:0")
+    assert ei.value.status == -1
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array([0, 5]), 10, 2, 10, 5, precision=7, device="cuda:0")
+    assert ei.value.status == -1
+
+
+def test_null_plan_and_pointers_rejected():
+    _ensure_built()
+    L = gce.lib()
+    assert L.gce_plan_execute(None, None, None, None, None, None, None, None) == -1
+    assert L.gce_plan_destroy(None) == 0
+    assert L.gce_plan_workspace_bytes(None) == 0
+    off = np.array([0, 4], dtype=np.int64)
+    rc = L.gce_search(None, None, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1,
+                      None, 3, None, 1, 10, 5, None, None, None)
+    assert rc == -1
+
+
+def test_valid_shape_needs_a_gfx950_device():
+    """With no GPU the host checks pass and device selection fails cleanly."""
+    _ensure_built()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array([0, 5, 9]), 10, 2, 10, 5, device="cuda:0")
+    assert ei.value.status == -5

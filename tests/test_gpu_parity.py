@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+FP64 path contract: histogram counts bit-exact (debug-count hook), every CE
+value within the derived tolerance, per-curve minima identical (or tied within
+tolerance).  Katz et al. 2020, Sec. 2.3, Eqs. (3)-(4).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2006_06866_amd as gce
+from paper_2006_06866_amd import synth
+from gce_testlib import (say, to_dev, upload, ce_tolerance, run_gpu, assert_cube_close,
+                         assert_best_valid, check_counts_exact)
+
+pytestmark = pytest.mark.gpu
+
+
+def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0):
+    say(f"[parity] {label}: curves={w.n_curves} N={w.lengths.tolist()[:8]} "
+        f"n_p={w.periods.size} n_pd={w.pdots.size} bins={w.n_phase}x{w.n_mag} "
+        f"tq={trials_per_lane}")
+    plan, dev, cube, best = run_gpu(w, trials_per_lane=trials_per_lane)
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                 w.n_phase, w.n_mag)
+    gc = cube.cpu().numpy()
+    bf = gce.best_fields(best)
+    assert_cube_close(gc, oc, w, label)
+    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, label)
+    assert np.array_equal(bf["period_index"], bf["flat_index"] % w.periods.size)
+    assert np.array_equal(bf["pdot_index"], bf["flat_index"] // w.periods.size)
+    rng = np.random.default_rng(seed)
+    n_tr = w.periods.size * w.pdots.size
+    ci = rng.integers(0, w.n_curves, counts_sample)
+    fi = rng.integers(0, n_tr, counts_sample)
+    ci = np.concatenate([ci, np.arange(w.n_curves)])
+    fi = np.concatenate([fi, bf["flat_index"]])
+    check_counts_exact(plan, dev, w, ci, fi, label)
+    plan.close()
+
+
+def test_c1_single_curve_full():
+    w = synth.make_config(1)
+    _full_parity(w, "c1")
+    # the injected period is recovered
+    _, best = run_gpu(w, want_cube=False)[2:]
+    assert gce.best_fields(best)["flat_index"][0] == w.truth["inj_p"][0]
+
+
+EDGE_LENGTHS = [1, 2, 3, 63, 64, 65, 127, 300, 1000]
+
+
+@pytest.mark.parametrize("n_phase,n_mag,tq", [
+    (10, 5, 0), (10, 5, 1), (10, 5, 2), (10, 5, 4), (10, 5, 8),
+    (15, 5, 0), (20, 10, 0), (20, 10, 8), (50, 10, 0), (50, 10, 4),
+    (7, 3, 0), (7, 3, 8), (1, 1, 0), (2, 2, 0), (128, 5, 1), (33, 255, 2),
+])
+def test_ragged_small_grid(n_phase, n_mag, tq):
+    w = synth.random_curves(20 + n_phase + 7 * tq, EDGE_LENGTHS, n_freq=150,
+                            n_pdots=7, n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
+    _full_parity(w, f"ragged nph={n_phase} nmag={n_mag}", trials_per_lane=tq)
+
+
+def test_single_pdot_and_single_period():
+    w = synth.random_curves(31, [5, 70, 130], n_freq=1, n_pdots=1)
+    _full_parity(w, "1x1 grid")
+    w = synth.random_curves(32, [5, 70, 130], n_freq=65, n_pdots=1)
+    _full_parity(w, "Pdot axis of one")
+
+
+def test_dyadic_bin_edges_and_negative_phase():
+    """Phases exactly on bin edges (dyadic inputs) and folds whose argument
+    y = x - Pdot x^2 / 2 is negative, including -1 < y < 0 where y - floor(y)
+    rounds: the GPU bins must equal the oracle's bit for bit."""
+    rng = np.random.default_rng(40)
+    ts, ms = [], []
+    # dyadic epochs, power-of-two periods: exact phases, many on bin edges
+    for _ in range(3):
+        k = rng.integers(0, 1 << 12, 200)
+        ts.append(10.0 + k / 64.0)
+        ms.append(rng.integers(0, 9, 200) / 8.0)
+    # y just below zero: x slightly beyond 1/a with a = Pdot/2 = 0.25, P = 1
+    d = 4.0 + 10.0 ** rng.uniform(-15, -2, 300)
+    ts.append(np.concatenate([[0.0], d]))
+    ms.append(rng.uniform(size=301))
+    off = np.zeros(len(ts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([x.size for x in ts])
+    periods = np.array([0.25, 0.125, 0.0625, 1.0, 0.5, 1.0 / 3.0])
+    pdots = np.array([0.0, 2.0 ** -12, -2.0 ** -12, 0.5, 0.9, -0.5])
+    w = synth.Workload("edges", np.concatenate(ts), np.concatenate(ms), off, periods,
+                       pdots, 8, 4)
+    _full_parity(w, "dyadic edges", counts_sample=0)
+    plan, dev, _, _ = run_gpu(w, want_cube=False)
+    ci = np.repeat(np.arange(w.n_curves), periods.size * pdots.size)
+    fi = np.tile(np.arange(periods.size * pdots.size), w.n_curves)
+    check_counts_exact(plan, dev, w, ci, fi, "dyadic edges all trials")
+    for nph in (10, 50):
+        w2 = synth.Workload("edges", w.times, w.mags, off, periods, pdots, nph, 4)
+        plan, dev, _, _ = run_gpu(w2, want_cube=False)
+        check_counts_exact(plan, dev, w2, ci, fi, f"dyadic edges nph={nph}")
+
+
+def test_constant_magnitudes_and_single_epoch():
+    w = synth.random_curves(33, [1, 2, 50, 200], n_freq=70, n_pdots=3)
+    w.mags[w.offsets[2]:w.offsets[3]] = 1.25        # constant curve
+    plan, dev, cube, best = run_gpu(w)
+    gc = cube.cpu().numpy()
+    bf = gce.best_fields(best)
+    for c in (0, 2):                                # N = 1 and constant
+        assert np.all(gc[c] == 0.0), c
+        assert bf["flat_index"][c] == 0 and bf["ce_min"][c] == 0.0
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5)
+    assert_cube_close(gc, oc, w, "constant")
+
+
+def test_invalid_values_mark_curves():
+    w = synth.random_curves(34, [40, 50, 60], n_freq=70, n_pdots=3)
+    mags = w.mags.copy()
+    mags[w.offsets[1] + 7] = np.nan
+    w_bad = synth.Workload("bad", w.times, mags, w.offsets, w.periods, w.pdots, 10, 5)
+    plan, dev, cube, best = run_gpu(w_bad)
+    gc = cube.cpu().numpy()
+    bf = gce.best_fields(best)
+    assert bf["flat_index"].tolist()[1] == -1 and math.isnan(bf["ce_min"][1])
+    assert np.all(np.isnan(gc[1]))
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5)
+    keep = [0, 2]
+    sub = w.subset(keep)
+    assert_cube_close(gc[keep], oc[keep], sub, "valid curves beside a NaN curve")
+    assert np.array_equal(bf["flat_index"][keep], obf[keep])
+    # a bad period invalidates every curve
+    periods = w.periods.copy()
+    periods[5] = -1.0
+    t, m, P, Pd = upload(w)
+    P = to_dev(periods)
+    plan = gce.Plan(w.offsets, periods.size, w.pdots.size, 10, 5)
+    cube2, best2 = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    assert np.all(gce.best_fields(best2)["flat_index"] == -1)
+    assert torch.isnan(cube2).all().item()
+    # a NaN Pdot too
+    pdots = w.pdots.copy()
+    pdots[1] = np.nan
+    _, best3 = plan.execute(t, m, to_dev(w.periods), to_dev(pdots))
+    torch.cuda.synchronize()
+    assert np.all(gce.best_fields(best3)["flat_index"] == -1)
+
+
+def test_best_only_equals_full_and_is_deterministic():
+    w = synth.random_curves(35, [33, 600, 250, 1], n_freq=300, n_pdots=9)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 10, 5)
+    c1, b1 = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    _, b2 = plan.execute(t, m, P, Pd)
+    c3, b3 = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    # bitwise: the statistics fields hold NaN when statistics are off
+    assert torch.equal(b1.view(torch.int64), b2.view(torch.int64))
+    assert torch.equal(b1.view(torch.int64), b3.view(torch.int64))
+    assert torch.equal(c1, c3)
+
+
+def test_one_call_search_matches_plan():
+    w = synth.random_curves(36, [80, 90], n_freq=100, n_pdots=4)
+    t, m, P, Pd = upload(w)
+    cube, best = gce.search(t, m, w.offsets, P, Pd, 10, 5)
+    torch.cuda.synchronize()
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5)
+    assert_cube_close(cube.cpu().numpy(), oc, w, "gce_search")
+    assert np.array_equal(gce.best_fields(best)["flat_index"], obf)
+
+
+def test_graph_replay_matches_eager():
+    w = synth.random_curves(37, [100, 500, 20], n_freq=200, n_pdots=8)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 10, 5)
+    ref_c, ref_b = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    ref_c, ref_b = ref_c.clone(), ref_b.clone()
+    cube, best = plan.new_cube(), plan.new_best()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.execute(t, m, P, Pd, out_ce=cube, out_best=best, stream=s)   # warm
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(t, m, P, Pd, out_ce=cube, out_best=best,
+                     stream=torch.cuda.current_stream())
+    for i in range(4):
+        cube.fill_(-1.0)
+        best.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(cube, ref_c), i
+        assert torch.equal(best.view(torch.int64), ref_b.view(torch.int64)), i
+
+
+def test_c2_slice_full_grid():
+    """Eight curves of the batched workload over its full 20,000 x 64 grid."""
+    w = synth.make_config(2).subset(np.arange(8))
+    say("[parity] c2 slice: 8 curves, full grid")
+    plan, dev, cube, best = run_gpu(w, want_cube=True)
+    gc = cube.cpu().numpy()
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                 w.n_phase, w.n_mag)
+    assert_cube_close(gc, oc, w, "c2 slice")
+    bf = gce.best_fields(best)
+    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "c2 slice")
+    rng = np.random.default_rng(41)
+    ci = rng.integers(0, w.n_curves, 2000)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, 2000)
+    check_counts_exact(plan, dev, w, ci, fi, "c2 slice counts")

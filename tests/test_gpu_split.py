@@ -1,0 +1,100 @@
+"""Split-precision path (FP32 Pdot term and binning, FP64 entropy).
+
+Its bins approximate the FP64 reference, so the checks are:
+  * self-consistency: every CE value equals Eq. (4) of the histogram the
+    split binning produces (debug hook, same device bin code), to FP32
+    output rounding;
+  * against the FP64 oracle: count-mismatch rate, |dH|, and the recovered
+    minimum (strictly equal, or within 1e-5 of the oracle's minimum CE).
+Katz et al. 2020, Sec. 2.3, Eqs. (3)-(4).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2006_06866_amd as gce
+from paper_2006_06866_amd import synth
+from gce_testlib import say, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _split_run(w, tq=0):
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
+                    precision=gce.PRECISION_SPLIT_FP32, trials_per_lane=tq)
+    cube, best = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    return plan, (t, m, P, Pd), cube.cpu().numpy(), gce.best_fields(best)
+
+
+def _self_consistency(plan, dev, w, gcube, n_sample, seed):
+    rng = np.random.default_rng(seed)
+    ci = rng.integers(0, w.n_curves, n_sample)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, n_sample)
+    cnt = plan.debug_counts(*dev, ci, fi).cpu().numpy().astype(np.uint32)
+    assert np.all(cnt.sum(axis=(1, 2)) == w.lengths[ci])
+    h_own = np.array([oracle.entropy(c) for c in cnt])
+    q, p = np.divmod(fi, w.periods.size)
+    h_gpu = gcube[ci, q, p].astype(np.float64)
+    # FP32 output rounding plus FP64 entropy rounding
+    assert np.all(np.abs(h_gpu - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12)
+    return ci, fi, cnt
+
+
+@pytest.mark.parametrize("n_phase,n_mag,tq", [
+    (10, 5, 0), (10, 5, 2), (10, 5, 4), (20, 10, 0), (20, 10, 8), (15, 5, 4),
+    (50, 10, 2), (7, 3, 8), (1, 1, 0), (100, 5, 1),
+])
+def test_split_self_consistent_and_close(n_phase, n_mag, tq):
+    w = synth.random_curves(60 + n_phase + tq, [1, 2, 63, 64, 65, 300, 1000], n_freq=150,
+                            n_pdots=7, n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
+    say(f"[split] nph={n_phase} nmag={n_mag} tq={tq}")
+    plan, dev, gcube, bf = _split_run(w, tq)
+    ci, fi, cnt = _self_consistency(plan, dev, w, gcube, 600, n_phase)
+    _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, n_phase,
+                            n_mag, ci, fi, want_counts=True)
+    moved = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2
+    rate = moved / w.lengths[ci].sum()
+    say(f"[split] count mismatch rate {rate:.2e}")
+    assert rate <= 1e-4
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                 n_phase, n_mag)
+    # the minimum the split path picks is (near) the FP64 minimum
+    for c in range(w.n_curves):
+        q, p = divmod(int(bf["flat_index"][c]), w.periods.size)
+        assert oc[c, q, p] <= obc[c] + 1e-5 or bf["flat_index"][c] == obf[c], c
+
+
+def test_split_lds_limit_is_reported():
+    # 128 phase bins plus the wrap slot and the marginals exceed 64 KiB of LDS
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array([0, 10]), 5, 1, 128, 5, precision=gce.PRECISION_SPLIT_FP32)
+    assert ei.value.status == -6
+
+
+def test_split_c2_slice_agreement():
+    """Eight curves of the batched workload, full 20,000 x 64 grid."""
+    w = synth.make_config(2).subset(np.arange(8))
+    say("[split] c2 slice")
+    plan, dev, gcube, bf = _split_run(w)
+    _self_consistency(plan, dev, w, gcube, 3000, 7)
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                 w.n_phase, w.n_mag)
+    dh = np.abs(gcube.astype(np.float64) - oc)
+    frac_ok = np.mean(dh <= 1e-5)
+    say(f"[split] c2 slice: max|dH|={dh.max():.3e} frac(|dH|<=1e-5)={frac_ok:.6f} "
+        f"strict best {np.sum(bf['flat_index'] == obf)}/8")
+    assert frac_ok > 0.99
+    assert np.array_equal(bf["flat_index"], obf)
+
+
+def test_split_constant_and_invalid():
+    w = synth.random_curves(70, [1, 40, 50], n_freq=70, n_pdots=3)
+    w.mags[w.offsets[1]:w.offsets[2]] = 3.0
+    w.mags[w.offsets[2] + 3] = np.inf
+    plan, dev, gcube, bf = _split_run(w)
+    assert np.all(gcube[0] == 0.0) and np.all(gcube[1] == 0.0)
+    assert bf["flat_index"][0] == 0 and bf["flat_index"][1] == 0
+    assert bf["flat_index"][2] == -1 and np.all(np.isnan(gcube[2]))
