@@ -53,16 +53,17 @@ def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
     return 4.0 + 2.0 / n_pd + (n_phase * (n_mag + 1) + 2) / mean_n
 
 
-def valu_instr_per_point_trial(precision, n_pd):
-    """VALU instructions the kernel's design needs per point-trial.
-
-    FP64: fma, fract, mul, cvt and the histogram address per point-trial;
-    x and x^2 per point-period.  Split: fma, fract, rounding fma and the
-    address per point-trial; x, x^2, frac(x) - shift and two conversions to
-    float per point-period."""
+def valu_instr_per_point_trial(precision, tq):
+    """VALU instructions the kernel executes per point-trial in its fold and
+    binning (the per-segment entropy flush, ~0.3 more at 600 epochs, is not
+    counted).  FP64: fma, fract, mul, cvt and the histogram address per
+    point-trial; x and x^2 per epoch and lane, shared by the lane's tq Pdot
+    trials.  Split: fma, fract, rounding fma and the address per point-trial;
+    x, x^2, frac(x), the half-bin shift and two conversions to float per
+    epoch and lane."""
     if precision == 0:
-        return 5.0 + 2.0 / n_pd
-    return 4.0 + 6.0 / n_pd
+        return 5.0 + 2.0 / tq
+    return 4.0 + 6.0 / tq
 
 
 def cpu_baseline(w, gpu_cube_rows, budget_s):
@@ -102,7 +103,12 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
              "argmin_equal": f"{best_agree}/{best_checked}"})
 
 
-def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube_on):
+def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube_on,
+              graph=False):
+    """Warm up, then time exactly `steps` whole searches.  With graph=True the
+    search (all four kernels) is captured once in a HIP graph and the timed
+    steps are graph replays; the search kernel's own duration then comes
+    from a separate eager pass with events."""
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
                     precision=precision, trials_per_lane=tq, device=dev)
     cube = plan.new_cube() if cube_on else None
@@ -111,13 +117,26 @@ def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube
     for _ in range(warmup):
         plan.execute(*inputs, out_ce=cube, out_best=best, stream=stream)
     torch.cuda.synchronize()
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.execute(*inputs, out_ce=cube, out_best=best,
+                         stream=torch.cuda.current_stream(dev))
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     plan.set_timing(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.execute(*inputs, out_ce=cube, out_best=best, stream=stream)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    if not graph:
+        elapsed = time.perf_counter() - t0
     kernel_ms = plan.search_times_ms()
     plan.set_timing(0)
     return plan, cube, best, elapsed, float(np.mean(kernel_ms)) / 1e3
@@ -143,13 +162,13 @@ def measured_traffic(config, precision):
     return rec.get("per_launch_bytes", {}).get(key)
 
 
-def roofline(precision, w, kernel_s, config):
+def roofline(precision, w, kernel_s, config, tq):
     pt = w.point_trials
     mean_n = float(w.lengths.mean())
     fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag, mean_n)
     achieved = fpp * pt / kernel_s / 1e12
     peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
-    instr = valu_instr_per_point_trial(precision, w.pdots.size)
+    instr = valu_instr_per_point_trial(precision, tq)
     return {
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak, "traffic": measured_traffic(config, precision),
@@ -169,6 +188,8 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="minimum only (no CE cube)")
     ap.add_argument("--trials-per-lane", type=int, default=0)
     ap.add_argument("--no-split", action="store_true", help="skip the split leg")
+    ap.add_argument("--graph", action="store_true",
+                    help="time HIP-graph replays of the whole search")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU-baseline budget; 0 skips the oracle leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -209,7 +230,7 @@ def main():
 
     plan64, cube64, best64, el64, k64 = timed_leg(
         gce, torch, np, w, dev, inputs, 0, args.trials_per_lane, args.steps,
-        args.warmup, cube_on)
+        args.warmup, cube_on, args.graph)
     log(f"fp64: {el64 / args.steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
     value = pt * args.steps / el64
     bf64 = gce.best_fields(best64)
@@ -233,8 +254,9 @@ def main():
             "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
             "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
             "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
+            "timing": "hip-graph replay" if args.graph else "eager launches",
         },
-        "roofline": roofline(0, w, k64, args.config),
+        "roofline": roofline(0, w, k64, args.config, plan64.info()["trials_per_lane"]),
     }
     has = w.truth["inj_p"] >= 0
     out["recovery_fp64"] = {
@@ -248,7 +270,7 @@ def main():
     if not args.no_split:
         plan32, cube32, best32, el32, k32 = timed_leg(
             gce, torch, np, w, dev, inputs, 1, args.trials_per_lane, args.steps,
-            args.warmup, cube_on)
+            args.warmup, cube_on, args.graph)
         log(f"split: {el32 / args.steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
         bf32 = gce.best_fields(best32)
         strict = int(np.sum(bf32["flat_index"] == bf64["flat_index"]))
@@ -257,7 +279,7 @@ def main():
             "ms_per_step": el32 / args.steps * 1e3,
             "speedup_vs_fp64": el64 / el32,
             "trials_per_lane": plan32.info()["trials_per_lane"],
-            "roofline": roofline(1, w, k32, args.config),
+            "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"]),
             "best_equal_strict": f"{strict}/{w.n_curves}",
         }
         if cube_on:

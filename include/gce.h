@@ -68,16 +68,16 @@ extern "C" {
 #define GCE_PRECISION_SPLIT_FP32 1  /* FP32 Pdot term and binning, FP64 entropy;
                                        approximate bins, FP32 CE cube */
 
-/* Per-curve result (40 bytes). */
+/* Per-curve result (48 bytes). */
 typedef struct {
     int64_t flat_index;   /* q * n_periods + p of the minimum; -1 if invalid */
     int32_t period_index; /* p; -1 if invalid */
     int32_t pdot_index;   /* q; -1 if invalid */
     double ce_min;        /* H_c at flat_index; NaN if invalid */
-    double ce_mean;       /* mean of H_c over the grid (Eq. (5)); NaN unless
-                             statistics were requested */
-    double ce_std;        /* population std of H_c over the grid; NaN unless
-                             statistics were requested */
+    double ce_mean;       /* mean of H_c over the curve's trials; NaN if invalid */
+    double ce_std;        /* population standard deviation of those H_c */
+    double significance;  /* Eq. (5): (ce_mean - ce_min) / ce_std; 0 when
+                             ce_std = 0; NaN if invalid */
 } gce_best_t;
 
 /*
@@ -115,8 +115,7 @@ typedef struct {
     int32_t precision;       /* GCE_PRECISION_* */
     int32_t trials_per_lane; /* Pdot trials per lane: 0 = automatic, else
                                 1, 2, 4 or 8 */
-    int32_t statistics;      /* nonzero: fill ce_mean / ce_std (Eq. (5)) */
-    int32_t reserved;
+    int32_t reserved[2];     /* must be 0 */
 } gce_opts;
 
 /*
@@ -125,7 +124,7 @@ typedef struct {
  * workspace and upload the per-curve metadata.  Synchronous.
  *  plan          : out, the new plan.
  *  curve_offsets : HOST, [n_curves + 1] as for gce_search (copied).
- *  opts          : may be NULL (FP64, automatic tiling, no statistics).
+ *  opts          : may be NULL (FP64, automatic tiling).
  *  device        : HIP device ordinal the plan runs on.
  */
 int gce_plan_create(gce_plan_t *plan, const int64_t *curve_offsets,
@@ -192,6 +191,27 @@ typedef struct {
 
 /* Fill *info for the plan.  Returns GCE_EINVAL for NULL arguments. */
 int gce_plan_get_info(gce_plan_t plan, gce_plan_info_t *info);
+
+/*
+ * gce_merge_results -- combine per-curve results of searches over parts of
+ * one grid (Sec. 4: batches over Pdot values or periods keep their minimum and
+ * statistics, and the batches are combined).  HOST arrays, no GPU work.
+ *  acc        : [n_curves] running result, flat indices in the full grid.
+ *  acc_trials : trials already merged into acc (the same for every curve);
+ *               0 means acc is empty and is overwritten.
+ *  part       : [n_curves] result of one execute over the sub-grid of
+ *               part_n_periods periods starting at period part_p_offset and
+ *               part_n_pdots Pdot values starting at part_q_offset.
+ *  n_periods  : period count of the full grid.
+ * The minimum is the lexicographic (H_c, full-grid flat index) minimum, the
+ * mean and population standard deviation are merged exactly (Chan et al.),
+ * and the significance is recomputed.  Invalid curves stay invalid.
+ */
+int gce_merge_results(gce_best_t *acc, int64_t acc_trials,
+                      const gce_best_t *part, int64_t n_curves,
+                      int64_t n_periods, int64_t part_p_offset,
+                      int64_t part_n_periods, int64_t part_q_offset,
+                      int64_t part_n_pdots);
 
 /* Bytes of device workspace the plan holds. */
 size_t gce_plan_workspace_bytes(gce_plan_t plan);

@@ -71,6 +71,7 @@ def _load():
                                          _i64, ctypes.c_int64, _d, _u32,
                                          ctypes.c_int32]
         lib.ce_oracle_max_threads.restype = ctypes.c_int
+        lib.ce_oracle_significance.argtypes = [_d, ctypes.c_int64, _d, _d, _d]
         _lib = lib
     return _lib
 
@@ -191,3 +192,21 @@ def trials(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
                                   _p(cnt, _u32), n_threads)
     _check(rc, "trials")
     return (ce, cnt) if want_counts else ce
+
+
+def significance(values):
+    """Eq. (5) inputs over one curve's CE values: (mean, population std,
+    rho = (mean - min) / std, 0 when std = 0)."""
+    v = _f64(values).ravel()
+    mean, sd, rho = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = _load().ce_oracle_significance(_p(v, _d), v.size, ctypes.byref(mean),
+                                        ctypes.byref(sd), ctypes.byref(rho))
+    _check(rc, "significance")
+    return mean.value, sd.value, rho.value
+
+
+def curve_statistics(cube):
+    """Per-curve (mean, std, rho) arrays of a [n_curves, ...] CE cube."""
+    c = np.asarray(cube, dtype=np.float64).reshape(cube.shape[0], -1)
+    out = np.array([significance(row) for row in c])
+    return out[:, 0], out[:, 1], out[:, 2]

@@ -460,6 +460,32 @@ int ce_oracle_trials(const double *times, const double *mags,
     return fail ? ORACLE_ENOMEM : ORACLE_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Eq. (5) and its inputs: over one curve's n CE values, the mean, the
+ * population standard deviation (two passes) and the significance
+ * rho = (mean - min) / std, taken as 0 when std = 0.
+ * ------------------------------------------------------------------------- */
+int ce_oracle_significance(const double *values, int64_t n, double *mean,
+                           double *std_dev, double *rho)
+{
+    if (!values || n < 1 || !mean || !std_dev || !rho)
+        return ORACLE_EINVAL;
+    double sum = 0.0, lo = values[0];
+    for (int64_t i = 0; i < n; ++i) {
+        sum += values[i];
+        if (values[i] < lo) lo = values[i];
+    }
+    const double mu = sum / (double)n;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        ss += (values[i] - mu) * (values[i] - mu);
+    const double sd = sqrt(ss / (double)n);
+    *mean = mu;
+    *std_dev = sd;
+    *rho = sd > 0.0 ? (mu - lo) / sd : 0.0;
+    return ORACLE_OK;
+}
+
 int ce_oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -19,7 +19,7 @@ import numpy as np
 import torch  # imported first: the library then shares torch's HIP runtime
 
 __all__ = [
-    "GceError", "Plan", "search", "best_fields", "lib", "LIB_PATH",
+    "GceError", "Plan", "search", "best_fields", "merge_results", "lib", "LIB_PATH",
     "PRECISION_FP64", "PRECISION_SPLIT_FP32",
 ]
 
@@ -32,8 +32,9 @@ GCE_OK = 0
 STATUS_NAMES = {0: "GCE_OK", -1: "GCE_EINVAL", -2: "GCE_ENOMEM", -3: "GCE_EHIP",
                 -4: "GCE_EWORKSPACE", -5: "GCE_ENODEV", -6: "GCE_EUNSUPPORTED"}
 
-# gce_best_t is 40 bytes: int64 flat, int32 p, int32 q, double min/mean/std.
-BEST_WORDS = 5
+# gce_best_t is 48 bytes: int64 flat, int32 p, int32 q, double min, mean,
+# std, significance.
+BEST_WORDS = 6
 
 
 class GceError(RuntimeError):
@@ -50,7 +51,7 @@ class _Info(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
-                ("statistics", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib():
         L.gce_plan_destroy.argtypes = [_vp]
         L.gce_plan_set_timing.argtypes = [_vp, _i32]
         L.gce_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+        L.gce_merge_results.argtypes = [_vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _i64]
         L.gce_plan_search_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), _i32,
                                             ctypes.POINTER(_i32)]
         _lib = L
@@ -120,8 +122,11 @@ def _stream_handle(stream, device) -> ctypes.c_void_p:
 
 
 def best_fields(best: torch.Tensor) -> dict:
-    """Split a [n_curves, 5] gce_best_t tensor into numpy fields."""
-    raw = best.detach().cpu().contiguous().numpy().view(np.uint8).reshape(best.shape[0], 40)
+    """Split a [n_curves, 6] gce_best_t tensor (or a host array of the same
+    bytes) into numpy fields."""
+    if isinstance(best, torch.Tensor):
+        best = best.detach().cpu().contiguous().numpy()
+    raw = np.ascontiguousarray(best).view(np.uint8).reshape(-1, 8 * BEST_WORDS)
     return {
         "flat_index": raw[:, 0:8].copy().view(np.int64).ravel(),
         "period_index": raw[:, 8:12].copy().view(np.int32).ravel(),
@@ -129,6 +134,7 @@ def best_fields(best: torch.Tensor) -> dict:
         "ce_min": raw[:, 16:24].copy().view(np.float64).ravel(),
         "ce_mean": raw[:, 24:32].copy().view(np.float64).ravel(),
         "ce_std": raw[:, 32:40].copy().view(np.float64).ravel(),
+        "significance": raw[:, 40:48].copy().view(np.float64).ravel(),
     }
 
 
@@ -137,8 +143,7 @@ class Plan:
 
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
-                 trials_per_lane: int = 0, statistics: bool = False,
-                 device: Optional[torch.device] = None):
+                 trials_per_lane: int = 0, device: Optional[torch.device] = None):
         self._h = None
         self.offsets = _host_offsets(offsets)
         self.n_curves = int(self.offsets.size - 1)
@@ -149,7 +154,7 @@ class Plan:
         if self.device.index is None:
             idx = torch.cuda.current_device() if torch.cuda.is_available() else 0
             self.device = torch.device("cuda", idx)
-        opts = _Opts(self.precision, int(trials_per_lane), int(bool(statistics)), 0)
+        opts = _Opts(self.precision, int(trials_per_lane), 0, 0)
         h = ctypes.c_void_p()
         L = lib()
         _check(L.gce_plan_create(ctypes.byref(h),
@@ -246,6 +251,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def merge_results(acc: Optional[np.ndarray], acc_trials: int, part, n_periods: int,
+                  part_p_offset: int, part_n_periods: int, part_q_offset: int,
+                  part_n_pdots: int) -> np.ndarray:
+    """Combine the per-curve results of a search over a sub-grid into a running
+    result (gce_merge_results).  part: [n_curves, 6] tensor or array as
+    returned by execute; acc: host array of the same shape or None.  Returns
+    the updated host array."""
+    if isinstance(part, torch.Tensor):
+        part = part.detach().cpu().contiguous().numpy()
+    part = np.ascontiguousarray(part, dtype=np.float64)
+    if acc is None:
+        acc = np.empty_like(part)
+        acc_trials = 0
+    _check(lib().gce_merge_results(acc.ctypes.data_as(_vp), int(acc_trials),
+                                   part.ctypes.data_as(_vp), part.shape[0],
+                                   int(n_periods), int(part_p_offset),
+                                   int(part_n_periods), int(part_q_offset),
+                                   int(part_n_pdots)))
+    return acc
 
 
 def search(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Tensor,

@@ -72,14 +72,15 @@ int choose_tq(int precision, int n_phase, int64_t n_pd, int requested)
 {
     if (requested > 0) return requested;
     // Pdot trials per lane: more trials share each point's x and x^2, but
-    // every trial adds histogram LDS and registers.  Measured on MI355X
-    // (512 x 600 epochs, 20,000 x 64 grid, 10 phase bins): both kernels are
-    // fastest at 8 (FP64 8/4/2: 60/64/73 ms; split 8/4: 51/54 ms).
-    (void)precision;
+    // every trial pair adds a histogram region of LDS.  Measured on MI355X:
+    // 8 trials is fastest while a wave's histograms stay near 10 KiB (10
+    // phase bins: FP64 8/4/2 trials 60/64/73 ms at 512 x 600 x 20,000 x 64);
+    // at 20 KiB (20 bins) the CU holds too few waves and 4 trials wins
+    // (64 x 5,000 x 100,000 x 256: 1.25 s at 4 vs 1.70 s at 8).
     int tq = 8;
     while (tq > 1 && (tq >= 2 * n_pd ||
                       !gce::search_variant_exists(precision, n_phase, tq) ||
-                      gce::search_lds_bytes(precision, n_phase, tq) > 24 * 1024))
+                      gce::search_lds_bytes(precision, n_phase, tq) > 13 * 1024))
         tq /= 2;
     return tq;
 }
@@ -187,8 +188,8 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     if (o.trials_per_lane != 0 && o.trials_per_lane != 1 && o.trials_per_lane != 2 &&
         o.trials_per_lane != 4 && o.trials_per_lane != 8)
         return fail(GCE_EINVAL, "trials_per_lane must be 0, 1, 2, 4 or 8");
-    if (o.statistics)
-        return fail(GCE_EUNSUPPORTED, "statistics are not built in this library");
+    if (o.reserved[0] != 0 || o.reserved[1] != 0)
+        return fail(GCE_EINVAL, "reserved option fields must be 0");
     const int tq = choose_tq(o.precision, n_phase_bins, n_pdots, o.trials_per_lane);
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
@@ -221,7 +222,6 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.n_units = n_curves * dp.units_per_curve;
     dp.max_n = max_n;
     dp.precision = o.precision;
-    dp.statistics = o.statistics;
     if (dp.n_units > 0x7fffffffll) {
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
@@ -255,6 +255,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     const size_t o_hpd = take(sizeof(double) * (size_t)n_pdots);
     const size_t o_hpd32 = take(sizeof(float) * (size_t)n_pdots);
     const size_t o_part = take(sizeof(gce::Partial) * (size_t)dp.n_units);
+    const size_t o_stats = take(sizeof(gce::UnitStats) * (size_t)dp.n_units);
     pl->ws_bytes = sz;
 
     hipError_t e = hipMalloc(&pl->ws, sz);
@@ -276,7 +277,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.half_pd = reinterpret_cast<double *>(w + o_hpd);
     dp.half_pd32 = reinterpret_cast<float *>(w + o_hpd32);
     dp.partials = reinterpret_cast<gce::Partial *>(w + o_part);
-    dp.stats = nullptr;
+    dp.stats = reinterpret_cast<gce::UnitStats *>(w + o_stats);
 
     e = hipMemcpy(const_cast<int64_t *>(dp.off), curve_offsets,
                   sizeof(int64_t) * (size_t)(n_curves + 1), hipMemcpyHostToDevice);
@@ -351,6 +352,54 @@ int gce_plan_debug_counts(gce_plan_t pl, const double *times,
 }
 
 size_t gce_plan_workspace_bytes(gce_plan_t pl) { return pl ? pl->ws_bytes : 0; }
+
+int gce_merge_results(gce_best_t *acc, int64_t acc_trials, const gce_best_t *part,
+                      int64_t n_curves, int64_t n_periods, int64_t part_p_offset,
+                      int64_t part_n_periods, int64_t part_q_offset,
+                      int64_t part_n_pdots)
+{
+    if (!acc || !part || n_curves < 1 || acc_trials < 0 || n_periods < 1 ||
+        part_p_offset < 0 || part_n_periods < 1 || part_q_offset < 0 ||
+        part_n_pdots < 1 || part_p_offset + part_n_periods > n_periods)
+        return fail(GCE_EINVAL, "bad merge arguments");
+    const double nb = (double)part_n_periods * (double)part_n_pdots;
+    const double na = (double)acc_trials;
+    for (int64_t c = 0; c < n_curves; ++c) {
+        gce_best_t in = part[c];
+        if (in.flat_index >= 0) {   // to full-grid indices
+            const int64_t q = in.flat_index / part_n_periods + part_q_offset;
+            const int64_t p = in.flat_index % part_n_periods + part_p_offset;
+            in.flat_index = q * n_periods + p;
+            in.period_index = (int32_t)p;
+            in.pdot_index = (int32_t)q;
+        }
+        gce_best_t &a = acc[c];
+        if (acc_trials == 0) {
+            a = in;
+            continue;
+        }
+        if (a.flat_index < 0 || in.flat_index < 0) {   // invalid stays invalid
+            a.flat_index = -1;
+            a.period_index = a.pdot_index = -1;
+            a.ce_min = a.ce_mean = a.ce_std = a.significance = NAN;
+            continue;
+        }
+        if (in.ce_min < a.ce_min || (in.ce_min == a.ce_min && in.flat_index < a.flat_index)) {
+            a.flat_index = in.flat_index;
+            a.period_index = in.period_index;
+            a.pdot_index = in.pdot_index;
+            a.ce_min = in.ce_min;
+        }
+        const double n = na + nb;
+        const double d = in.ce_mean - a.ce_mean;
+        const double m2 = a.ce_std * a.ce_std * na + in.ce_std * in.ce_std * nb +
+                          d * d * (na * nb / n);
+        a.ce_mean = a.ce_mean + d * (nb / n);
+        a.ce_std = std::sqrt(m2 / n);
+        a.significance = a.ce_std > 0.0 ? (a.ce_mean - a.ce_min) / a.ce_std : 0.0;
+    }
+    return GCE_OK;
+}
 
 int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
 {

@@ -26,6 +26,14 @@ struct Partial {
     int64_t flat;
 };
 
+// Moments of one work unit's CE values: count, mean, sum of squared
+// deviations from the mean (merged per curve for Eq. (5)).
+struct UnitStats {
+    double n;
+    double mean;
+    double m2;
+};
+
 // Everything a kernel needs: the shape, the schedule and views into the
 // plan's device workspace.  Passed to kernels by value.
 struct DevPlan {
@@ -41,7 +49,6 @@ struct DevPlan {
     int64_t n_units;          // n_curves * units_per_curve
     int32_t max_n;            // longest curve
     int32_t precision;
-    int32_t statistics;
 
     // plan-time metadata
     const int64_t *off;       // [n_curves + 1] curve offsets
@@ -58,7 +65,7 @@ struct DevPlan {
     double *half_pd;          // [n_pd] Pdot / 2
     float *half_pd32;         // [n_pd] Pdot / 2 rounded to float (split path)
     Partial *partials;        // [n_units]
-    double *stats;            // [n_units][2] sum and sum of squares (or NULL)
+    UnitStats *stats;         // [n_units]
 };
 
 // Kernel launchers (gce_kernels.hip).  Each returns the launch status.

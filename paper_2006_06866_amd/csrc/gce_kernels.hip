@@ -84,6 +84,31 @@ __device__ __forceinline__ bool lex_less(double h1, int64_t f1, double h2,
     return (h1 < h2) || (h1 == h2 && f1 < f2);
 }
 
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Chan et al. pairwise update of (count, mean, M2) with another part.
+__device__ __forceinline__ void moments_merge(double &n, double &mean, double &m2,
+                                              double nb, double mb, double m2b)
+{
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb;
+        mean = mb;
+        m2 = m2b;
+        return;
+    }
+    const double nn = n + nb;
+    const double d = mb - mean;
+    mean += d * (nb / nn);
+    m2 += m2b + d * d * (n * nb / nn);
+    n = nn;
+}
+
 __device__ __forceinline__ void wave_argmin(double &h, int64_t &f)
 {
 #pragma unroll
@@ -375,7 +400,10 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
                 if (q0 + t < dp.n_pd)
                     out_ce[((int64_t)c * dp.n_pd + q0 + t) * dp.n_p + p] = (OutT)NAN;
         }
-        if (lane == 0) dp.partials[u] = Partial{NAN, -1};
+        if (lane == 0) {
+            dp.partials[u] = Partial{NAN, -1};
+            dp.stats[u] = UnitStats{0.0, 0.0, 0.0};
+        }
         return;
     }
 
@@ -528,21 +556,40 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
     const double nd = (double)n;
     double best_h = NAN;
     int64_t best_f = -1;
+    double hv[TQ];
+    double lsum = 0.0, lcnt = 0.0;
 #pragma unroll
     for (int t = 0; t < TQ; ++t) {
         const OutT h = (OutT)((s2[t] - s1[t]) / nd);
+        hv[t] = (double)h;
         const int32_t q = q0 + t;
         if (p_ok && q < dp.n_pd) {
             const int64_t flat = (int64_t)q * dp.n_p + p;
             if (out_ce) out_ce[((int64_t)c * dp.n_pd + q) * dp.n_p + p] = h;
-            if (lex_less((double)h, flat, best_h, best_f)) {
-                best_h = (double)h;
+            if (lex_less(hv[t], flat, best_h, best_f)) {
+                best_h = hv[t];
                 best_f = flat;
             }
+            lsum += hv[t];
+            lcnt += 1.0;
         }
     }
     wave_argmin(best_h, best_f);
-    if (lane == 0) dp.partials[u] = Partial{best_h, best_f};
+    // moments of this unit's CE values (two passes over registers)
+    const double wcnt = wave_sum(lcnt);
+    const double wmean = wave_sum(lsum) / wcnt;
+    double lm2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t)
+        if (p_ok && q0 + t < dp.n_pd) {
+            const double d = hv[t] - wmean;
+            lm2 += d * d;
+        }
+    const double wm2 = wave_sum(lm2);
+    if (lane == 0) {
+        dp.partials[u] = Partial{best_h, best_f};
+        dp.stats[u] = UnitStats{wcnt, wmean, wm2};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,17 +671,38 @@ __global__ __launch_bounds__(kEpiBlock) void k_epilogue(DevPlan dp,
 {
     __shared__ double sh_h[kEpiBlock / kWave];
     __shared__ int64_t sh_f[kEpiBlock / kWave];
+    __shared__ double sh_n[kEpiBlock], sh_mean[kEpiBlock], sh_m2[kEpiBlock];
     const int64_t rank = blockIdx.x;
     const int32_t c = dp.order[rank];
     const Partial *pp = dp.partials + rank * dp.units_per_curve;
+    const UnitStats *ps = dp.stats + rank * dp.units_per_curve;
     double h = NAN;
     int64_t f = -1;
+    double n = 0.0, mean = 0.0, m2 = 0.0;
     for (int64_t i = threadIdx.x; i < dp.units_per_curve; i += kEpiBlock) {
         const Partial v = pp[i];
         if (lex_less(v.h, v.flat, h, f)) {
             h = v.h;
             f = v.flat;
         }
+        const UnitStats st = ps[i];
+        moments_merge(n, mean, m2, st.n, st.mean, st.m2);
+    }
+    // moments: fixed-order tree over the block (deterministic)
+    sh_n[threadIdx.x] = n;
+    sh_mean[threadIdx.x] = mean;
+    sh_m2[threadIdx.x] = m2;
+    __syncthreads();
+    for (int half = kEpiBlock / 2; half >= 1; half >>= 1) {
+        if (threadIdx.x < half) {
+            double a = sh_n[threadIdx.x], b = sh_mean[threadIdx.x], d = sh_m2[threadIdx.x];
+            moments_merge(a, b, d, sh_n[threadIdx.x + half], sh_mean[threadIdx.x + half],
+                          sh_m2[threadIdx.x + half]);
+            sh_n[threadIdx.x] = a;
+            sh_mean[threadIdx.x] = b;
+            sh_m2[threadIdx.x] = d;
+        }
+        __syncthreads();
     }
     wave_argmin(h, f);
     const int w = threadIdx.x / kWave;
@@ -650,13 +718,15 @@ __global__ __launch_bounds__(kEpiBlock) void k_epilogue(DevPlan dp,
                 f = sh_f[i];
             }
         gce_best_t b;
-        const bool ok = dp.curve_ok[c] && *dp.grid_ok && f >= 0;
+        const bool ok = dp.curve_ok[c] && *dp.grid_ok && f >= 0 && sh_n[0] > 0.0;
         b.flat_index = ok ? f : -1;
         b.period_index = ok ? (int32_t)(f % dp.n_p) : -1;
         b.pdot_index = ok ? (int32_t)(f / dp.n_p) : -1;
         b.ce_min = ok ? h : NAN;
-        b.ce_mean = NAN;
-        b.ce_std = NAN;
+        const double sd = sqrt(sh_m2[0] / sh_n[0]);
+        b.ce_mean = ok ? sh_mean[0] : NAN;
+        b.ce_std = ok ? sd : NAN;
+        b.significance = ok ? (sd > 0.0 ? (sh_mean[0] - h) / sd : 0.0) : NAN;
         out_best[c] = b;
     }
 }

@@ -32,6 +32,7 @@ def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0):
     assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, label)
     assert np.array_equal(bf["period_index"], bf["flat_index"] % w.periods.size)
     assert np.array_equal(bf["pdot_index"], bf["flat_index"] // w.periods.size)
+    _check_statistics(bf, oc, w, label)
     rng = np.random.default_rng(seed)
     n_tr = w.periods.size * w.pdots.size
     ci = rng.integers(0, w.n_curves, counts_sample)
@@ -40,6 +41,23 @@ def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0):
     fi = np.concatenate([fi, bf["flat_index"]])
     check_counts_exact(plan, dev, w, ci, fi, label)
     plan.close()
+
+
+def _check_statistics(bf, oc, w, label):
+    """Eq. (5) inputs against the oracle's two-pass moments of its own cube:
+    every CE value is within tol of the oracle's, so the mean and the
+    population std are too (both are 1-Lipschitz in the max norm), plus
+    summation rounding."""
+    om, osd, orho = oracle.curve_statistics(oc)
+    tol = ce_tolerance(np.abs(oc).reshape(w.n_curves, -1).max(axis=1), w.n_phase,
+                       w.n_mag, w.lengths)
+    n = oc[0].size
+    rnd = 4 * n * 2.0 ** -53 * np.abs(om) + 1e-15
+    assert np.all(np.abs(bf["ce_mean"] - om) <= tol + rnd), label
+    assert np.all(np.abs(bf["ce_std"] - osd) <= 2 * tol + rnd + 1e-12 * osd), label
+    ok = osd > 1e-9
+    rel = np.abs(bf["significance"][ok] - orho[ok]) / (1 + np.abs(orho[ok]))
+    assert np.all(rel <= (4 * tol[ok] + rnd[ok]) / osd[ok] + 1e-9), label
 
 
 def test_c1_single_curve_full():
@@ -216,3 +234,32 @@ def test_c2_slice_full_grid():
     ci = rng.integers(0, w.n_curves, 2000)
     fi = rng.integers(0, w.periods.size * w.pdots.size, 2000)
     check_counts_exact(plan, dev, w, ci, fi, "c2 slice counts")
+
+
+@pytest.mark.parametrize("axis", ["pdot", "period"])
+def test_batches_merge_to_single_search(axis):
+    """Searching parts of the grid and merging the per-curve results (Sec. 4)
+    gives the single search's minimum and statistics."""
+    w = synth.random_curves(38, [40, 300, 777, 5], n_freq=200, n_pdots=12)
+    t, m, P, Pd = upload(w)
+    whole = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 10, 5)
+    _, b = whole.execute(t, m, P, Pd)
+    torch.cuda.synchronize()
+    ref = gce.best_fields(b)
+    acc, trials = None, 0
+    if axis == "pdot":
+        cuts = [(0, 0, w.periods.size, 0, 5), (0, 0, w.periods.size, 5, 7)]
+    else:
+        cuts = [(0, 0, 70, 0, 12), (0, 70, 130, 0, 12)]
+    for _, pa, pn, qa, qn in cuts:
+        plan = gce.Plan(w.offsets, pn, qn, 10, 5)
+        _, bp = plan.execute(t, m, P[pa:pa + pn].contiguous(), Pd[qa:qa + qn].contiguous())
+        torch.cuda.synchronize()
+        acc = gce.merge_results(acc, trials, bp, w.periods.size, pa, pn, qa, qn)
+        trials += pn * qn
+    got = gce.best_fields(acc)
+    for k in ("flat_index", "period_index", "pdot_index", "ce_min"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.allclose(got["ce_mean"], ref["ce_mean"], rtol=0, atol=1e-13)
+    assert np.allclose(got["ce_std"], ref["ce_std"], rtol=1e-10, atol=1e-14)
+    assert np.allclose(got["significance"], ref["significance"], rtol=1e-8, atol=1e-10)

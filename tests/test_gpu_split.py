@@ -61,6 +61,10 @@ def test_split_self_consistent_and_close(n_phase, n_mag, tq):
     assert rate <= 1e-4
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
                                  n_phase, n_mag)
+    # statistics over the split path's own (float) CE values
+    own = gcube.astype(np.float64).reshape(w.n_curves, -1)
+    assert np.allclose(bf["ce_mean"], own.mean(axis=1), rtol=0, atol=1e-12)
+    assert np.allclose(bf["ce_std"], own.std(axis=1), rtol=1e-9, atol=1e-12)
     # the minimum the split path picks is (near) the FP64 minimum
     for c in range(w.n_curves):
         q, p = divmod(int(bf["flat_index"][c]), w.periods.size)

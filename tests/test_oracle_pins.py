@@ -323,3 +323,33 @@ def test_pdot_example_dephasing():
     late = dts > 0.8 * T
     assert np.mean(b0[late] != b1[late]) > 0.9
     assert np.all(b0[dts < 5.0] == b1[dts < 5.0])
+
+
+# --------------------------------------------------------------------------
+# Eq. (5) significance
+# --------------------------------------------------------------------------
+def test_significance_closed_forms():
+    m, s, r = oracle.significance([0.0, 1.0, 0.0, 1.0])
+    assert (m, s, r) == (0.5, 0.5, 1.0)
+    m, s, r = oracle.significance([2.5] * 7)
+    assert (m, s, r) == (2.5, 0.0, 0.0)
+    # one low outlier among n - 1 equal values: mean = 1 - 1/n,
+    # std = sqrt(n - 1) / n, rho = (n - 1) / sqrt(n - 1) = sqrt(n - 1)
+    n = 101
+    v = np.ones(n)
+    v[37] = 0.0
+    m, s, r = oracle.significance(v)
+    assert abs(m - (1 - 1 / n)) < 1e-15
+    assert abs(s - np.sqrt(n - 1) / n) < 1e-15
+    assert abs(r - np.sqrt(n - 1)) < 1e-12
+
+
+def test_significance_matches_library_moments():
+    rng = np.random.default_rng(17)
+    for _ in range(50):
+        v = rng.normal(1.5, rng.uniform(1e-4, 0.3), int(rng.integers(1, 5000)))
+        m, s, r = oracle.significance(v)
+        assert abs(m - np.mean(v)) <= 1e-14
+        assert abs(s - np.std(v)) <= 1e-13
+        if s > 0:
+            assert abs(r - (np.mean(v) - v.min()) / np.std(v)) <= 1e-9 * (1 + r)
