@@ -115,7 +115,11 @@ typedef struct {
     int32_t precision;       /* GCE_PRECISION_* */
     int32_t trials_per_lane; /* Pdot trials per lane: 0 = automatic, else
                                 1, 2, 4 or 8 */
-    int32_t reserved[2];     /* must be 0 */
+    int32_t phase_overlap;   /* nonzero: 50%-overlapping phase bins (Sec. 2.3):
+                                bin k spans phases [k, k + 2) / n_phase, wrapping,
+                                so every epoch counts in two bins and the
+                                probabilities of Eq. (4) are counts / (2N) */
+    int32_t reserved;        /* must be 0 */
 } gce_opts;
 
 /*
@@ -124,7 +128,7 @@ typedef struct {
  * workspace and upload the per-curve metadata.  Synchronous.
  *  plan          : out, the new plan.
  *  curve_offsets : HOST, [n_curves + 1] as for gce_search (copied).
- *  opts          : may be NULL (FP64, automatic tiling).
+ *  opts          : may be NULL (FP64, automatic tiling, disjoint bins).
  *  device        : HIP device ordinal the plan runs on.
  */
 int gce_plan_create(gce_plan_t *plan, const int64_t *curve_offsets,
@@ -212,6 +216,30 @@ int gce_merge_results(gce_best_t *acc, int64_t acc_trials,
                       int64_t n_periods, int64_t part_p_offset,
                       int64_t part_n_periods, int64_t part_q_offset,
                       int64_t part_n_pdots);
+
+/*
+ * gce_autotune -- measure the search kernel's Pdot-trials-per-lane choices
+ * (1, 2, 4, 8; those whose histograms fit in LDS) on a slice of the given
+ * workload and remember the fastest for its shape class: precision, phase and
+ * magnitude bin counts, Pdot count (1, 2, 3-4, 5-8, more) and median curve
+ * length (<128, <512, <2048, more).  Later plans created with automatic tiling
+ * (trials_per_lane = 0) in this process use the remembered choice.  If the
+ * environment variable GCE_TUNE_CACHE names a file, choices are read from it
+ * at the first plan creation and appended to it here.
+ * The slice: up to 128 curves spread over the length range, the first
+ * min(n_periods, 8192) periods, all Pdot values, minimum only (no cube).
+ * Inputs as for gce_search (times, mags, periods, pdots device; curve_offsets
+ * HOST).  Allocates and synchronises `stream`; not for graph capture.
+ *  best_tq  : out, the chosen trials per lane.
+ *  ms       : out (may be NULL), [4] search-kernel milliseconds for 1, 2, 4,
+ *             8 trials per lane; negative where a choice was not run.
+ */
+int gce_autotune(const double *times, const double *mags,
+                 const int64_t *curve_offsets, int64_t n_curves,
+                 const double *periods, int64_t n_periods, const double *pdots,
+                 int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
+                 int32_t precision, int32_t device, void *stream,
+                 int32_t *best_tq, float *ms);
 
 /* Bytes of device workspace the plan holds. */
 size_t gce_plan_workspace_bytes(gce_plan_t plan);

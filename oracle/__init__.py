@@ -56,10 +56,10 @@ def _load():
         lib.ce_oracle_entropy.restype = ctypes.c_double
         lib.ce_oracle_counts.argtypes = [_d, _d, ctypes.c_int64, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32,
-                                         ctypes.c_int32, _u32]
+                                         ctypes.c_int32, ctypes.c_int32, _u32]
         search_args = [_d, _d, _i64, ctypes.c_int64, _d, ctypes.c_int64, _d,
-                       ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _i64,
-                       _d, ctypes.c_int32]
+                       ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                       _d, _i64, _d, ctypes.c_int32]
         lib.ce_oracle_search.argtypes = search_args
         lib.ce_oracle_search_ponly.argtypes = [_d, _d, _i64, ctypes.c_int64, _d,
                                                ctypes.c_int64, ctypes.c_int32,
@@ -67,8 +67,8 @@ def _load():
                                                ctypes.c_int32]
         lib.ce_oracle_trials.argtypes = [_d, _d, _i64, ctypes.c_int64, _d,
                                          ctypes.c_int64, _d, ctypes.c_int64,
-                                         ctypes.c_int32, ctypes.c_int32, _i64,
-                                         _i64, ctypes.c_int64, _d, _u32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         _i64, _i64, ctypes.c_int64, _d, _u32,
                                          ctypes.c_int32]
         lib.ce_oracle_max_threads.restype = ctypes.c_int
         lib.ce_oracle_significance.argtypes = [_d, ctypes.c_int64, _d, _d, _d]
@@ -119,14 +119,16 @@ def entropy(counts) -> float:
 
 
 def counts(times, mags, period: float, pdot: float, n_phase: int,
-           n_mag: int) -> np.ndarray:
-    """[n_mag][n_phase] histogram of one curve at one (P, Pdot) trial."""
+           n_mag: int, phase_overlap: bool = False) -> np.ndarray:
+    """[n_mag][n_phase] histogram of one curve at one (P, Pdot) trial
+    (each epoch counted twice with 50%-overlapping phase bins)."""
     t, m = _f64(times), _f64(mags)
     if t.size != m.size:
         raise ValueError("times and mags differ in length")
     out = np.zeros((n_mag, n_phase), dtype=np.uint32)
     rc = _load().ce_oracle_counts(_p(t, _d), _p(m, _d), t.size, float(period),
-                                  float(pdot), n_phase, n_mag, _p(out, _u32))
+                                  float(pdot), n_phase, n_mag, int(phase_overlap),
+                                  _p(out, _u32))
     _check(rc, "counts")
     if rc == 1:
         raise ValueError("counts: non-finite input")
@@ -134,7 +136,7 @@ def counts(times, mags, period: float, pdot: float, n_phase: int,
 
 
 def search(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
-           want_cube: bool = True, n_threads: int = 0):
+           want_cube: bool = True, n_threads: int = 0, phase_overlap: bool = False):
     """Full grid search.  Returns (cube or None, best_flat, best_ce).
 
     cube is [n_curves][n_pdots][n_periods]; best_flat = q * n_periods + p.
@@ -148,8 +150,8 @@ def search(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
     bc = np.empty(nc)
     rc = _load().ce_oracle_search(_p(t, _d), _p(m, _d), _p(off, _i64), nc,
                                   _p(P, _d), P.size, _p(Pd, _d), Pd.size,
-                                  n_phase, n_mag, _p(cube, _d), _p(bf, _i64),
-                                  _p(bc, _d), n_threads)
+                                  n_phase, n_mag, int(phase_overlap), _p(cube, _d),
+                                  _p(bf, _i64), _p(bc, _d), n_threads)
     _check(rc, "search")
     return cube, bf, bc
 
@@ -174,7 +176,8 @@ def search_ponly(times, mags, offsets, periods, n_phase: int, n_mag: int,
 
 
 def trials(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
-           curve_ids, flat_ids, want_counts: bool = False, n_threads: int = 0):
+           curve_ids, flat_ids, want_counts: bool = False, n_threads: int = 0,
+           phase_overlap: bool = False):
     """H_c (and optionally counts) of selected (curve, flat) trials."""
     t, m = _f64(times), _f64(mags)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -187,8 +190,8 @@ def trials(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
     cnt = np.empty((ci.size, n_mag, n_phase), dtype=np.uint32) if want_counts else None
     rc = _load().ce_oracle_trials(_p(t, _d), _p(m, _d), _p(off, _i64),
                                   off.size - 1, _p(P, _d), P.size, _p(Pd, _d),
-                                  Pd.size, n_phase, n_mag, _p(ci, _i64),
-                                  _p(fi, _i64), ci.size, _p(ce, _d),
+                                  Pd.size, n_phase, n_mag, int(phase_overlap),
+                                  _p(ci, _i64), _p(fi, _i64), ci.size, _p(ce, _d),
                                   _p(cnt, _u32), n_threads)
     _check(rc, "trials")
     return (ce, cnt) if want_counts else ce

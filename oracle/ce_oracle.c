@@ -179,9 +179,13 @@ static void free_prep(curve_prep *cp)
     cp->mbin = NULL;
 }
 
-/* Histogram of one trial: counts[n_mag][n_phase] is cleared and filled. */
+/* Histogram of one trial: counts[n_mag][n_phase] is cleared and filled.
+ * With overlap, phase bin k spans [k, k + 2) / n_phase (wrapping), i.e. each
+ * bin overlaps each neighbour by half (Sec. 2.3): an epoch whose phase lies in
+ * [b, b + 1) / n_phase is inside bins b and b - 1 (mod n_phase), so every
+ * epoch is counted twice and the counts total 2N. */
 static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
-                         int ponly, int32_t n_phase, int32_t n_mag,
+                         int ponly, int overlap, int32_t n_phase, int32_t n_mag,
                          uint32_t *counts)
 {
     memset(counts, 0, (size_t)n_mag * (size_t)n_phase * sizeof(uint32_t));
@@ -189,6 +193,10 @@ static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
         int32_t b = ponly ? fold_bin_ponly(cp->dt[k], inv_p, n_phase)
                           : fold_bin(cp->dt[k], inv_p, half_pdot, n_phase);
         counts[(int64_t)cp->mbin[k] * n_phase + b] += 1;
+        if (overlap) {
+            int32_t prev = (b == 0) ? n_phase - 1 : b - 1;
+            counts[(int64_t)cp->mbin[k] * n_phase + prev] += 1;
+        }
     }
 }
 
@@ -199,7 +207,7 @@ static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
  * ------------------------------------------------------------------------- */
 int ce_oracle_counts(const double *times, const double *mags, int64_t n,
                      double period, double pdot, int32_t n_phase,
-                     int32_t n_mag, uint32_t *counts)
+                     int32_t n_mag, int32_t overlap, uint32_t *counts)
 {
     if (n <= 0 || n_phase < 1 || n_mag < 1 || !times || !mags || !counts)
         return ORACLE_EINVAL;
@@ -210,7 +218,8 @@ int ce_oracle_counts(const double *times, const double *mags, int64_t n,
     }
     int rc = cp.valid ? ORACLE_OK : 1;
     if (cp.valid)
-        trial_counts(&cp, 1.0 / period, 0.5 * pdot, 0, n_phase, n_mag, counts);
+        trial_counts(&cp, 1.0 / period, 0.5 * pdot, 0, overlap, n_phase, n_mag,
+                     counts);
     free_prep(&cp);
     return rc;
 }
@@ -236,6 +245,7 @@ static int check_offsets(const int64_t *off, int64_t n_curves)
  *   best_ce          : [n_curves] H_c at best_flat
  *   ponly            : nonzero => classic P-only fold, pdots ignored (n_pd
  *                      is still the size of the q axis of out_ce)
+ *   overlap          : nonzero => 50%-overlapping phase bins
  *   n_threads        : OpenMP threads over (curve, q); <= 0 = runtime default
  * The result does not depend on n_threads.
  * ------------------------------------------------------------------------- */
@@ -244,7 +254,8 @@ static int search_impl(const double *times, const double *mags,
                        const double *periods, int64_t n_p,
                        const double *pdots, int64_t n_pd, int32_t n_phase,
                        int32_t n_mag, double *out_ce, int64_t *best_flat,
-                       double *best_ce, int ponly, int32_t n_threads)
+                       double *best_ce, int ponly, int overlap,
+                       int32_t n_threads)
 {
     if (!times || !mags || !periods || (!pdots && !ponly) || !best_flat ||
         !best_ce || n_p < 1 || n_pd < 1 || n_phase < 1 || n_mag < 1)
@@ -311,8 +322,8 @@ static int search_impl(const double *times, const double *mags,
                 double half_pdot = ponly ? 0.0 : 0.5 * pdots[q];
                 for (int64_t p = 0; p < n_p; ++p) {
                     double inv_p = 1.0 / periods[p];
-                    trial_counts(cp, inv_p, half_pdot, ponly, n_phase, n_mag,
-                                 counts);
+                    trial_counts(cp, inv_p, half_pdot, ponly, overlap, n_phase,
+                                 n_mag, counts);
                     double h = ce_oracle_entropy(counts, n_mag, n_phase);
                     if (row)
                         row[p] = h;
@@ -357,11 +368,11 @@ int ce_oracle_search(const double *times, const double *mags,
                      const int64_t *off, int64_t n_curves,
                      const double *periods, int64_t n_p, const double *pdots,
                      int64_t n_pd, int32_t n_phase, int32_t n_mag,
-                     double *out_ce, int64_t *best_flat, double *best_ce,
-                     int32_t n_threads)
+                     int32_t overlap, double *out_ce, int64_t *best_flat,
+                     double *best_ce, int32_t n_threads)
 {
     return search_impl(times, mags, off, n_curves, periods, n_p, pdots, n_pd,
-                       n_phase, n_mag, out_ce, best_flat, best_ce, 0,
+                       n_phase, n_mag, out_ce, best_flat, best_ce, 0, overlap,
                        n_threads);
 }
 
@@ -375,7 +386,7 @@ int ce_oracle_search_ponly(const double *times, const double *mags,
                            int32_t n_threads)
 {
     return search_impl(times, mags, off, n_curves, periods, n_p, NULL, 1,
-                       n_phase, n_mag, out_ce, best_flat, best_ce, 1,
+                       n_phase, n_mag, out_ce, best_flat, best_ce, 1, 0,
                        n_threads);
 }
 
@@ -389,9 +400,9 @@ int ce_oracle_trials(const double *times, const double *mags,
                      const int64_t *off, int64_t n_curves,
                      const double *periods, int64_t n_p, const double *pdots,
                      int64_t n_pd, int32_t n_phase, int32_t n_mag,
-                     const int64_t *curve_ids, const int64_t *flat_ids,
-                     int64_t n_trials, double *out_ce, uint32_t *out_counts,
-                     int32_t n_threads)
+                     int32_t overlap, const int64_t *curve_ids,
+                     const int64_t *flat_ids, int64_t n_trials, double *out_ce,
+                     uint32_t *out_counts, int32_t n_threads)
 {
     if (!times || !mags || !periods || !pdots || !curve_ids || !flat_ids ||
         !out_ce || n_p < 1 || n_pd < 1 || n_phase < 1 || n_mag < 1 ||
@@ -447,8 +458,8 @@ int ce_oracle_trials(const double *times, const double *mags,
                            cells * sizeof(uint32_t));
                 continue;
             }
-            trial_counts(&cp, 1.0 / periods[p], 0.5 * pdots[q], 0, n_phase,
-                         n_mag, counts);
+            trial_counts(&cp, 1.0 / periods[p], 0.5 * pdots[q], 0, overlap,
+                         n_phase, n_mag, counts);
             out_ce[t] = ce_oracle_entropy(counts, n_mag, n_phase);
             if (out_counts)
                 memcpy(out_counts + (size_t)t * cells, counts,

@@ -19,7 +19,8 @@ import numpy as np
 import torch  # imported first: the library then shares torch's HIP runtime
 
 __all__ = [
-    "GceError", "Plan", "search", "best_fields", "merge_results", "lib", "LIB_PATH",
+    "GceError", "Plan", "search", "best_fields", "merge_results", "autotune", "lib",
+    "LIB_PATH",
     "PRECISION_FP64", "PRECISION_SPLIT_FP32",
 ]
 
@@ -51,7 +52,7 @@ class _Info(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("phase_overlap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -85,6 +86,9 @@ def lib():
         L.gce_plan_set_timing.argtypes = [_vp, _i32]
         L.gce_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
         L.gce_merge_results.argtypes = [_vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _i64]
+        L.gce_autotune.argtypes = [_vp, _vp, ctypes.POINTER(_i64), _i64, _vp, _i64, _vp, _i64,
+                                   _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32),
+                                   ctypes.POINTER(ctypes.c_float)]
         L.gce_plan_search_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), _i32,
                                             ctypes.POINTER(_i32)]
         _lib = L
@@ -143,7 +147,8 @@ class Plan:
 
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
-                 trials_per_lane: int = 0, device: Optional[torch.device] = None):
+                 trials_per_lane: int = 0, phase_overlap: bool = False,
+                 device: Optional[torch.device] = None):
         self._h = None
         self.offsets = _host_offsets(offsets)
         self.n_curves = int(self.offsets.size - 1)
@@ -154,7 +159,8 @@ class Plan:
         if self.device.index is None:
             idx = torch.cuda.current_device() if torch.cuda.is_available() else 0
             self.device = torch.device("cuda", idx)
-        opts = _Opts(self.precision, int(trials_per_lane), 0, 0)
+        self.phase_overlap = bool(phase_overlap)
+        opts = _Opts(self.precision, int(trials_per_lane), int(self.phase_overlap), 0)
         h = ctypes.c_void_p()
         L = lib()
         _check(L.gce_plan_create(ctypes.byref(h),
@@ -251,6 +257,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Tensor,
+             pdots: torch.Tensor, n_phase: int, n_mag: int,
+             precision: int = PRECISION_FP64, stream=None):
+    """Time the trials-per-lane choices on a slice of this workload and
+    remember the fastest for its shape class (gce_autotune).  Returns
+    (chosen trials per lane, {trials: kernel ms})."""
+    device = times.device
+    for name, x in (("times", times), ("mags", mags), ("periods", periods),
+                    ("pdots", pdots)):
+        _dev_f64(x, name, device)
+    off = _host_offsets(offsets)
+    tq = _i32(0)
+    ms = (ctypes.c_float * 4)()
+    _check(lib().gce_autotune(_ptr(times), _ptr(mags),
+                              off.ctypes.data_as(ctypes.POINTER(_i64)), off.size - 1,
+                              _ptr(periods), periods.numel(), _ptr(pdots), pdots.numel(),
+                              int(n_phase), int(n_mag), int(precision), device.index or 0,
+                              _stream_handle(stream, device), ctypes.byref(tq), ms))
+    return tq.value, {t: float(v) for t, v in zip((1, 2, 4, 8), ms) if v >= 0}
 
 
 def merge_results(acc: Optional[np.ndarray], acc_trials: int, part, n_periods: int,

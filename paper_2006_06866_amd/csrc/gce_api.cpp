@@ -4,6 +4,10 @@
 
 #include <algorithm>
 #include <cinttypes>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -68,9 +72,44 @@ int check_device(int dev)
     return GCE_OK;
 }
 
-int choose_tq(int precision, int n_phase, int64_t n_pd, int requested)
+// ---------------------------------------------------------------------------
+// tiling choice: autotuned per shape class, else a measured heuristic
+// ---------------------------------------------------------------------------
+using TuneKey = std::tuple<int, int, int, int, int>;   // prec, nph, nmag, pd class, N class
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+bool g_tune_file_read = false;
+
+int pdot_class(int64_t n_pd)
 {
-    if (requested > 0) return requested;
+    return n_pd <= 1 ? 0 : n_pd <= 2 ? 1 : n_pd <= 4 ? 2 : n_pd <= 8 ? 3 : 4;
+}
+
+int length_class(const int64_t *off, int64_t n_curves)
+{
+    std::vector<int64_t> len((size_t)n_curves);
+    for (int64_t c = 0; c < n_curves; ++c) len[(size_t)c] = off[c + 1] - off[c];
+    std::nth_element(len.begin(), len.begin() + n_curves / 2, len.end());
+    const int64_t med = len[(size_t)(n_curves / 2)];
+    return med < 128 ? 0 : med < 512 ? 1 : med < 2048 ? 2 : 3;
+}
+
+// GCE_TUNE_CACHE file: one "prec nph nmag pdclass nclass tq" line per choice.
+void read_tune_file_locked()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = std::getenv("GCE_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream in(path);
+    int a, b, c, d, e, tq;
+    while (in >> a >> b >> c >> d >> e >> tq)
+        if (tq == 1 || tq == 2 || tq == 4 || tq == 8) g_tuned[TuneKey{a, b, c, d, e}] = tq;
+}
+
+int heuristic_tq(int precision, int n_phase, int64_t n_pd)
+{
     // Pdot trials per lane: more trials share each point's x and x^2, but
     // every trial pair adds a histogram region of LDS.  Measured on MI355X:
     // 8 trials is fastest while a wave's histograms stay near 10 KiB (10
@@ -83,6 +122,21 @@ int choose_tq(int precision, int n_phase, int64_t n_pd, int requested)
                       gce::search_lds_bytes(precision, n_phase, tq) > 13 * 1024))
         tq /= 2;
     return tq;
+}
+
+int choose_tq(int precision, int n_phase, int n_mag, int64_t n_pd, const int64_t *off,
+              int64_t n_curves, int requested)
+{
+    if (requested > 0) return requested;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        read_tune_file_locked();
+        auto it = g_tuned.find(TuneKey{precision, n_phase, n_mag, pdot_class(n_pd),
+                                       length_class(off, n_curves)});
+        if (it != g_tuned.end() && gce::search_variant_exists(precision, n_phase, it->second))
+            return it->second;
+    }
+    return heuristic_tq(precision, n_phase, n_pd);
 }
 
 }  // namespace
@@ -188,9 +242,11 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     if (o.trials_per_lane != 0 && o.trials_per_lane != 1 && o.trials_per_lane != 2 &&
         o.trials_per_lane != 4 && o.trials_per_lane != 8)
         return fail(GCE_EINVAL, "trials_per_lane must be 0, 1, 2, 4 or 8");
-    if (o.reserved[0] != 0 || o.reserved[1] != 0)
-        return fail(GCE_EINVAL, "reserved option fields must be 0");
-    const int tq = choose_tq(o.precision, n_phase_bins, n_pdots, o.trials_per_lane);
+    if (o.reserved != 0) return fail(GCE_EINVAL, "reserved option field must be 0");
+    if (o.phase_overlap != 0 && o.phase_overlap != 1)
+        return fail(GCE_EINVAL, "phase_overlap must be 0 or 1");
+    const int tq = choose_tq(o.precision, n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
+                             n_curves, o.trials_per_lane);
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
     if (gce::search_lds_bytes(o.precision, n_phase_bins, tq) > 64 * 1024)
@@ -222,6 +278,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.n_units = n_curves * dp.units_per_curve;
     dp.max_n = max_n;
     dp.precision = o.precision;
+    dp.overlap = o.phase_overlap;
     if (dp.n_units > 0x7fffffffll) {
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
@@ -548,4 +605,121 @@ extern "C" int gce_search(const double *times, const double *mags,
     }
     return gce_plan_execute(plan, times, mags, periods, pdots, out_ce, out_best,
                             stream);
+}
+
+extern "C" int gce_autotune(const double *times, const double *mags,
+                            const int64_t *curve_offsets, int64_t n_curves,
+                            const double *periods, int64_t n_periods,
+                            const double *pdots, int64_t n_pdots,
+                            int32_t n_phase_bins, int32_t n_mag_bins,
+                            int32_t precision, int32_t device, void *stream,
+                            int32_t *best_tq, float *ms)
+{
+    int32_t max_n = 0;
+    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots, n_phase_bins,
+                            n_mag_bins, &max_n);
+    if (rc != GCE_OK) return rc;
+    if (!times || !mags || !periods || !pdots || !best_tq)
+        return fail(GCE_EINVAL, "NULL pointer");
+    if (precision != GCE_PRECISION_FP64 && precision != GCE_PRECISION_SPLIT_FP32)
+        return fail(GCE_EINVAL, "unknown precision");
+    rc = check_device(device);
+    if (rc != GCE_OK) return rc;
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // slice: up to 128 curves spread evenly over the length-sorted curves,
+    // gathered into one contiguous device buffer
+    std::vector<int64_t> idx((size_t)n_curves);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        return (curve_offsets[a + 1] - curve_offsets[a]) <
+               (curve_offsets[b + 1] - curve_offsets[b]);
+    });
+    const int64_t k = std::min<int64_t>(n_curves, 128);
+    std::vector<int64_t> pick((size_t)k), off((size_t)k + 1, 0);
+    for (int64_t i = 0; i < k; ++i) {
+        pick[(size_t)i] = idx[(size_t)((i * n_curves + n_curves / 2) / k)];
+        off[(size_t)i + 1] = off[(size_t)i] + curve_offsets[pick[(size_t)i] + 1] -
+                             curve_offsets[pick[(size_t)i]];
+    }
+    const int64_t np_slice = std::min<int64_t>(n_periods, 8192);
+    const int64_t tot = off[(size_t)k];
+    double *buf = nullptr;
+    gce_best_t *best = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&buf, sizeof(double) * (size_t)(2 * tot));
+    if (e == hipSuccess) e = hipMalloc(&best, sizeof(gce_best_t) * (size_t)k);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int64_t i = 0; i < k && e == hipSuccess; ++i) {
+        const int64_t a = curve_offsets[pick[(size_t)i]];
+        const size_t n = (size_t)(off[(size_t)i + 1] - off[(size_t)i]);
+        e = hipMemcpyAsync(buf + off[(size_t)i], times + a, n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(buf + tot + off[(size_t)i], mags + a, n * sizeof(double),
+                               hipMemcpyDeviceToDevice, s);
+    }
+    const int cands[4] = {1, 2, 4, 8};
+    float best_ms = -1.f;
+    int chosen = 0;
+    for (int ci = 0; ci < 4 && e == hipSuccess; ++ci) {
+        if (ms) ms[ci] = -1.f;
+        const int tq = cands[ci];
+        if (tq > 1 && tq >= 2 * n_pdots) continue;
+        if (!gce::search_variant_exists(precision, n_phase_bins, tq) ||
+            gce::search_lds_bytes(precision, n_phase_bins, tq) > 40 * 1024)
+            continue;
+        gce_opts o{};
+        o.precision = precision;
+        o.trials_per_lane = tq;
+        gce_plan_t pl = nullptr;
+        rc = gce_plan_create(&pl, off.data(), k, np_slice, n_pdots, n_phase_bins,
+                             n_mag_bins, &o, device);
+        if (rc != GCE_OK) continue;
+        float t_sum = 0.f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            // first execute warms up; the next two are timed
+            if (rep > 0) e = hipEventRecord(e0, s);
+            if (e == hipSuccess && gce_plan_execute(pl, buf, buf + tot, periods, pdots,
+                                                    nullptr, best, s) != GCE_OK)
+                e = hipErrorLaunchFailure;
+            if (rep > 0 && e == hipSuccess) e = hipEventRecord(e1, s);
+            if (rep > 0 && e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (rep > 0 && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            t_sum += t;
+        }
+        gce_plan_destroy(pl);
+        if (e != hipSuccess) break;
+        const float t = t_sum / 2.f;
+        if (ms) ms[ci] = t;
+        if (best_ms < 0.f || t < best_ms) {
+            best_ms = t;
+            chosen = tq;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+    if (best) (void)hipFree(best);
+    if (e != hipSuccess) return fail_hip(e, "autotune");
+    if (chosen == 0) return fail(GCE_EUNSUPPORTED, "no tiling fits this shape");
+    *best_tq = chosen;
+    const TuneKey key{precision, n_phase_bins, n_mag_bins, pdot_class(n_pdots),
+                      length_class(curve_offsets, n_curves)};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    read_tune_file_locked();
+    g_tuned[key] = chosen;
+    if (const char *path = std::getenv("GCE_TUNE_CACHE")) {
+        if (*path) {
+            std::ofstream out(path, std::ios::app);
+            out << precision << ' ' << n_phase_bins << ' ' << n_mag_bins << ' '
+                << pdot_class(n_pdots) << ' ' << length_class(curve_offsets, n_curves)
+                << ' ' << chosen << '\n';
+        }
+    }
+    return GCE_OK;
 }

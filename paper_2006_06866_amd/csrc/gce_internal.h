@@ -49,6 +49,7 @@ struct DevPlan {
     int64_t n_units;          // n_curves * units_per_curve
     int32_t max_n;            // longest curve
     int32_t precision;
+    int32_t overlap;          // 50%-overlapping phase bins
 
     // plan-time metadata
     const int64_t *off;       // [n_curves + 1] curve offsets

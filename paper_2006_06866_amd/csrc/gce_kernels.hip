@@ -467,18 +467,56 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
     };
 
     // end of a magnitude segment: sum c ln c, add to marginals, clear
-    auto flush_word = [&](int r, int b) -> uint32_t {
-        uint32_t *cell = hcol + (r * nslot + b) * kWave;
-        uint32_t w = *cell;
-        *cell = 0;
-        if (S::kWrap && b == 0) {
-            uint32_t *wrap = hcol + (r * nslot + nph) * kWave;
-            w += *wrap;
-            *wrap = 0;
-        }
+    auto cell = [&](int r, int b) -> uint32_t * { return hcol + (r * nslot + b) * kWave; };
+    auto add_lut = [&](int r, uint32_t w) {
         s1[2 * r] += lut[w & 0xffffu];
         if (2 * r + 1 < TQ) s1[2 * r + 1] += lut[w >> 16];
-        return w;
+    };
+    // One branch-free pass over the phase bins.  With 50%-overlapping bins,
+    // bin b spans disjoint bins b and b + 1 (mod n): its count is the sum of
+    // the two words (packed halves cannot overflow: together they hold at
+    // most the curve's N epochs); with disjoint bins the neighbour is masked
+    // to zero.  Bin 0's word (wrap slot merged) is kept in a register for
+    // the last bin, so every cell is cleared as soon as it is read.
+    const bool ovl = dp.overlap != 0;
+    const uint32_t nb_mask = ovl ? 0xffffffffu : 0u;
+    auto flush_segment = [&]() {
+        uint32_t w0[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w0[r] = *cell(r, 0);
+            if (S::kWrap) {   // the wrap slot belongs to bin 0
+                w0[r] += *cell(r, nph);
+                *cell(r, nph) = 0;
+            }
+        }
+        if constexpr (NPH > 0) {
+#pragma unroll
+            for (int b = 0; b < NPH; ++b) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
+                    const uint32_t wn = ((b + 1 < NPH) ? *cell(r, b + 1) : w0[r]) & nb_mask;
+                    *cell(r, b) = 0;
+                    vmarg[r][b] += w;
+                    add_lut(r, w + wn);
+                }
+                // bound the table loads in flight (register pressure): no
+                // memory access may move across this point
+                if ((b + 1) % S::kFlushGroup == 0) asm volatile("" ::: "memory");
+            }
+        } else {
+            for (int b = 0; b < nph; ++b) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
+                    const uint32_t wn = ((b + 1 < nph) ? *cell(r, b + 1) : w0[r]) & nb_mask;
+                    *cell(r, b) = 0;
+                    lmarg[(r * nph + b) * kWave + lane] += w;
+                    add_lut(r, w + wn);
+                }
+            }
+        }
     };
 
     for (int32_t j = 0; j < dp.n_mag; ++j) {
@@ -510,22 +548,7 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
         }
         for (; k < k1; ++k) fold_point(dts[k]);
 
-        if constexpr (NPH > 0) {
-#pragma unroll
-            for (int b = 0; b < NPH; ++b) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) vmarg[r][b] += flush_word(r, b);
-                // bound the table loads in flight (register pressure): no
-                // memory access may move across this point
-                if ((b + 1) % S::kFlushGroup == 0) asm volatile("" ::: "memory");
-            }
-        } else {
-            for (int b = 0; b < nph; ++b) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    lmarg[(r * nph + b) * kWave + lane] += flush_word(r, b);
-            }
-        }
+        flush_segment();
     }
 
     double s2[TQ];
@@ -544,16 +567,25 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
 #pragma unroll
             for (int r = 0; r < R; ++r) hcol[(r * nslot + b) * kWave] = vmarg[r][b];
 #pragma unroll 1
-        for (int b = 0; b < NPH; ++b)
+        for (int b = 0; b < NPH; ++b) {
+            const int bn = (b + 1 == NPH) ? 0 : b + 1;
 #pragma unroll
-            for (int r = 0; r < R; ++r) marg_word(r, hcol[(r * nslot + b) * kWave]);
+            for (int r = 0; r < R; ++r)
+                marg_word(r, hcol[(r * nslot + b) * kWave] +
+                                 (hcol[(r * nslot + bn) * kWave] & nb_mask));
+        }
     } else {
-        for (int b = 0; b < nph; ++b)
+        for (int b = 0; b < nph; ++b) {
+            const int bn = (b + 1 == nph) ? 0 : b + 1;
 #pragma unroll
-            for (int r = 0; r < R; ++r) marg_word(r, lmarg[(r * nph + b) * kWave + lane]);
+            for (int r = 0; r < R; ++r)
+                marg_word(r, lmarg[(r * nph + b) * kWave + lane] +
+                                 (lmarg[(r * nph + bn) * kWave + lane] & nb_mask));
+        }
     }
 
-    const double nd = (double)n;
+    // probabilities are counts / N, or counts / (2N) with overlapping bins
+    const double nd = ovl ? 2.0 * (double)n : (double)n;
     double best_h = NAN;
     int64_t best_f = -1;
     double hv[TQ];
@@ -776,6 +808,12 @@ __global__ __launch_bounds__(64) void k_debug_counts(
             }
             b = b < 0 ? 0 : (b >= nph ? nph - 1 : b);
             o[(int64_t)j * nph + b] += 1;
+        }
+        if (dp.overlap) {   // bin b spans disjoint bins b and b + 1 (mod n)
+            uint32_t *row = o + (int64_t)j * nph;
+            const uint32_t first = row[0];
+            for (int32_t b = 0; b < nph; ++b)
+                row[b] += (b + 1 < nph) ? row[b + 1] : first;
         }
     }
 }

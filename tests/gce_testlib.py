@@ -31,15 +31,17 @@ def ce_tolerance(h_ref, n_phase, n_mag, n_points):
     (terms + 2) * 2^-53 * ln N on H, doubled for the table and the oracle's
     own rounding.  Plus 1e-12 relative, the agreement the method promises.
     """
-    n = np.maximum(np.asarray(n_points, dtype=np.float64), 2.0)
+    n = np.maximum(2.0 * np.asarray(n_points, dtype=np.float64), 2.0)
     terms = n_phase * (n_mag + 1) + 2
     return 1e-12 * np.abs(h_ref) + 2.0 * terms * 2.0 ** -53 * np.log(n)
 
 
-def run_gpu(w, want_cube=True, trials_per_lane=0, stream=None):
+def run_gpu(w, want_cube=True, trials_per_lane=0, stream=None, phase_overlap=False,
+            precision=0):
     t, m, P, Pd = upload(w)
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
-                    trials_per_lane=trials_per_lane)
+                    trials_per_lane=trials_per_lane, phase_overlap=phase_overlap,
+                    precision=precision)
     cube = plan.new_cube() if want_cube else None
     cube, best = plan.execute(t, m, P, Pd, out_ce=cube, stream=stream)
     torch.cuda.synchronize()
@@ -77,12 +79,15 @@ def check_counts_exact(plan, dev_inputs, w, curve_ids, flat_ids, label=""):
     got = plan.debug_counts(t, m, P, Pd, curve_ids, flat_ids)
     torch.cuda.synchronize()
     got = got.cpu().numpy().astype(np.uint32)
+    ovl = getattr(plan, "phase_overlap", False)
     _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
-                            w.n_mag, curve_ids, flat_ids, want_counts=True)
+                            w.n_mag, curve_ids, flat_ids, want_counts=True,
+                            phase_overlap=ovl)
     if not np.array_equal(got, want):
         bad = np.argwhere(np.any(got != want, axis=(1, 2))).ravel()
         i = int(bad[0])
         raise AssertionError(f"{label}: {bad.size} of {len(curve_ids)} trial histograms differ; "
                              f"first trial curve={curve_ids[i]} flat={flat_ids[i]}\n"
                              f"gpu={got[i].tolist()}\noracle={want[i].tolist()}")
-    assert np.all(got.sum(axis=(1, 2)) == w.lengths[np.asarray(curve_ids)])
+    mult = 2 if ovl else 1
+    assert np.all(got.sum(axis=(1, 2)) == mult * w.lengths[np.asarray(curve_ids)])

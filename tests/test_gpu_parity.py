@@ -19,13 +19,15 @@ from gce_testlib import (say, to_dev, upload, ce_tolerance, run_gpu, assert_cube
 pytestmark = pytest.mark.gpu
 
 
-def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0):
+def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0,
+                 phase_overlap=False):
     say(f"[parity] {label}: curves={w.n_curves} N={w.lengths.tolist()[:8]} "
         f"n_p={w.periods.size} n_pd={w.pdots.size} bins={w.n_phase}x{w.n_mag} "
-        f"tq={trials_per_lane}")
-    plan, dev, cube, best = run_gpu(w, trials_per_lane=trials_per_lane)
+        f"tq={trials_per_lane} overlap={phase_overlap}")
+    plan, dev, cube, best = run_gpu(w, trials_per_lane=trials_per_lane,
+                                    phase_overlap=phase_overlap)
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
-                                 w.n_phase, w.n_mag)
+                                 w.n_phase, w.n_mag, phase_overlap=phase_overlap)
     gc = cube.cpu().numpy()
     bf = gce.best_fields(best)
     assert_cube_close(gc, oc, w, label)
@@ -263,3 +265,34 @@ def test_batches_merge_to_single_search(axis):
     assert np.allclose(got["ce_mean"], ref["ce_mean"], rtol=0, atol=1e-13)
     assert np.allclose(got["ce_std"], ref["ce_std"], rtol=1e-10, atol=1e-14)
     assert np.allclose(got["significance"], ref["significance"], rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("n_phase,n_mag,tq", [
+    (10, 5, 0), (10, 5, 8), (50, 10, 0), (15, 5, 4), (7, 3, 2), (2, 2, 0), (1, 1, 0),
+    (20, 10, 8),
+])
+def test_overlapping_phase_bins(n_phase, n_mag, tq):
+    """50%-overlapping phase bins (Sec. 2.3): counts bit-exact and CE within
+    tolerance of the oracle, which counts each epoch in the two bins whose
+    spans contain its phase."""
+    w = synth.random_curves(80 + n_phase + tq, EDGE_LENGTHS, n_freq=130, n_pdots=6,
+                            n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
+    _full_parity(w, f"overlap nph={n_phase}", trials_per_lane=tq, phase_overlap=True)
+
+
+def test_overlap_rejects_nothing_and_differs_from_disjoint():
+    w = synth.random_curves(90, [300, 400], n_freq=80, n_pdots=2)
+    _, _, c0, _ = run_gpu(w)
+    _, _, c1, _ = run_gpu(w, phase_overlap=True)
+    torch.cuda.synchronize()
+    assert not torch.equal(c0, c1)
+
+
+def test_autotune_picks_a_measured_tiling():
+    w = synth.make_config(2).subset(np.arange(64))
+    t, m, P, Pd = upload(w)
+    tq, ms = gce.autotune(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag)
+    say(f"[autotune] chose {tq}: {ms}")
+    assert tq in ms and ms[tq] == min(ms.values())
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
+    assert plan.info()["trials_per_lane"] == tq

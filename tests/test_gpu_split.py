@@ -71,6 +71,28 @@ def test_split_self_consistent_and_close(n_phase, n_mag, tq):
         assert oc[c, q, p] <= obc[c] + 1e-5 or bf["flat_index"][c] == obf[c], c
 
 
+def test_split_overlap_self_consistent():
+    w = synth.random_curves(95, [2, 64, 300, 1000], n_freq=150, n_pdots=7, pdot_scale=5e-9)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 10, 5,
+                    precision=gce.PRECISION_SPLIT_FP32, phase_overlap=True)
+    cube, best = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    g = cube.cpu().numpy()
+    rng = np.random.default_rng(3)
+    ci = rng.integers(0, w.n_curves, 500)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, 500)
+    cnt = plan.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy().astype(np.uint32)
+    assert np.all(cnt.sum(axis=(1, 2)) == 2 * w.lengths[ci])
+    h_own = np.array([oracle.entropy(c) for c in cnt])
+    q, p = np.divmod(fi, w.periods.size)
+    assert np.all(np.abs(g[ci, q, p] - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12)
+    _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5, ci, fi,
+                            want_counts=True, phase_overlap=True)
+    rate = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2 / (2 * w.lengths[ci].sum())
+    assert rate <= 1e-4
+
+
 def test_split_lds_limit_is_reported():
     # 128 phase bins plus the wrap slot and the marginals exceed 64 KiB of LDS
     with pytest.raises(gce.GceError) as ei:

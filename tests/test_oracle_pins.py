@@ -110,10 +110,11 @@ def test_fold_close_to_exact_on_generic_inputs():
 def test_counts_hand(golden_dir):
     g = _golden(golden_dir, "counts_hand.json")
     for case in g["cases"]:
+        ovl = case.get("phase_overlap", False)
         c = oracle.counts(case["times"], case["mags"], case["period"], case["pdot"],
-                          case["n_phase"], case["n_mag"])
+                          case["n_phase"], case["n_mag"], phase_overlap=ovl)
         assert c.tolist() == case["counts"], case["name"]
-        assert c.sum() == len(case["times"])
+        assert c.sum() == len(case["times"]) * (2 if ovl else 1)
         h = oracle.entropy(c)
         assert abs(h - case["entropy"]) <= 1e-15, case["name"]
 
@@ -353,3 +354,54 @@ def test_significance_matches_library_moments():
         assert abs(s - np.std(v)) <= 1e-13
         if s > 0:
             assert abs(r - (np.mean(v) - v.min()) / np.std(v)) <= 1e-9 * (1 + r)
+
+
+# --------------------------------------------------------------------------
+# 50%-overlapping phase bins (Sec. 2.3)
+# --------------------------------------------------------------------------
+def _exact_phase(dt, period, pdot):
+    dt, P, Pd = Fraction(dt), Fraction(period), Fraction(pdot)
+    y = dt / P - Pd * dt * dt / (2 * P * P)
+    return y - math.floor(y)
+
+
+@pytest.mark.parametrize("n_phase", [1, 2, 5, 8, 10])
+def test_overlap_counts_by_interval_membership(n_phase):
+    """Bin k spans [k, k + 2) / n (mod 1): count, for every epoch and bin,
+    whether the exact phase lies inside; compare with the oracle."""
+    t, m, off, periods, pdots = _dyadic_workload(30 + n_phase, n_curves=2, n_points=40)
+    n_mag = 4
+    for c in range(2):
+        tc, mc = t[off[c]:off[c + 1]], m[off[c]:off[c + 1]]
+        dt = tc - tc.min()
+        jbin = np.minimum((mc * n_mag).astype(int), n_mag - 1)
+        for P in periods[:4]:
+            for Pd in pdots:
+                want = np.zeros((n_mag, n_phase), dtype=np.int64)
+                for d, j in zip(dt, jbin):
+                    phi = _exact_phase(d, P, Pd)
+                    for k in range(n_phase):
+                        rel = (phi - Fraction(k, n_phase)) % 1
+                        if rel < Fraction(2, n_phase) or n_phase == 1:
+                            want[j, k] += 1 if n_phase > 1 else 2
+                got = oracle.counts(tc, mc, P, Pd, n_phase, n_mag, phase_overlap=True)
+                assert np.array_equal(got, want), (c, P, Pd)
+                h = oracle.entropy(got)
+                assert abs(h - _conditional_entropy_scipy(want)) <= 1e-13
+
+
+def test_overlap_search_consistent_with_counts():
+    w = synth.random_curves(41, [30, 200], n_freq=40, n_pdots=3)
+    cube, bf, bc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                                 phase_overlap=True)
+    ids = np.arange(w.periods.size * w.pdots.size)
+    for c in range(2):
+        h = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                          np.full(ids.size, c), ids, phase_overlap=True)
+        assert np.array_equal(h, cube[c].ravel())
+        t, m = w.curve(c)
+        for f in (0, 17, ids.size - 1):
+            q, p = divmod(int(f), w.periods.size)
+            cnt = oracle.counts(t, m, w.periods[p], w.pdots[q], 10, 5, phase_overlap=True)
+            assert cnt.sum() == 2 * t.size
+            assert abs(oracle.entropy(cnt) - cube[c, q, p]) == 0.0
