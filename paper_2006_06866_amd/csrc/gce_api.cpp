@@ -176,6 +176,9 @@ int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
 {
     if (!off) return fail(GCE_EINVAL, "curve_offsets is NULL");
     if (n_curves < 1) return fail(GCE_EINVAL, "n_curves must be >= 1");
+    // one 256-thread block per curve in the per-curve kernels: the dispatch
+    // grid (work-items) must stay below 2^32
+    if (n_curves > 16000000) return fail(GCE_EINVAL, "more than 16,000,000 curves");
     if (n_p < 1 || n_pd < 1) return fail(GCE_EINVAL, "grid sizes must be >= 1");
     if (n_phase < 1 || n_phase > gce::kMaxPhaseBins)
         return fail(GCE_EINVAL, "n_phase_bins out of range [1, 128]");
@@ -279,7 +282,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.max_n = max_n;
     dp.precision = o.precision;
     dp.overlap = o.phase_overlap;
-    if (dp.n_units > 0x7fffffffll) {
+    if (dp.n_units > gce::kMaxUnits) {
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
     }

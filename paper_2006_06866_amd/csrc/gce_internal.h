@@ -19,6 +19,10 @@ constexpr double kMaxSpanDays = 1e12;
 constexpr double kMinPeriod = 1e-12;
 constexpr double kMaxPeriod = 1e12;
 constexpr double kMaxAbsPdot = 1.0;
+// Search launches are 2-D: at most this many one-wave blocks along x (the
+// dispatch grid size counts work-items in 32 bits), up to 65,535 rows.
+constexpr int64_t kSearchGridX = 65536;
+constexpr int64_t kMaxUnits = kSearchGridX * 65535;
 
 // Minimum of one work unit: smallest H_c and its flat index (-1: none).
 struct Partial {

@@ -381,7 +381,10 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
     const int lane = threadIdx.x;
     const int nph = NPH > 0 ? NPH : dp.n_phase;
     const int nslot = nph + S::kWrap;                   // LDS words per region
-    const int64_t u = blockIdx.x;
+    // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
+    // unit = y * gridDim.x + x, in dispatch order
+    const int64_t u = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (u >= dp.n_units) return;
     const int64_t rank = u / dp.units_per_curve;
     const int64_t rem = u - rank * dp.units_per_curve;
     const int32_t g = (int32_t)(rem / dp.n_ptiles);
@@ -688,7 +691,9 @@ hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
     const Variant *v = find_variant(dp.precision, dp.n_phase, dp.tq);
     if (!v) return hipErrorInvalidValue;
     const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq);
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)dp.n_units), dim3(kWave), lds, s,
+    const int64_t gx = dp.n_units < kSearchGridX ? dp.n_units : kSearchGridX;
+    const int64_t gy = (dp.n_units + gx - 1) / gx;
+    hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave), lds, s,
                        dp, out_ce);
     return hipGetLastError();
 }

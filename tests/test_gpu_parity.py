@@ -296,3 +296,40 @@ def test_autotune_picks_a_measured_tiling():
     assert tq in ms and ms[tq] == min(ms.values())
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
     assert plan.info()["trials_per_lane"] == tq
+
+
+def test_search_beyond_32bit_dispatch_grid():
+    """More than 2^32 work-items of search waves (regression: a 1-D launch
+    wrapped its 32-bit grid size and skipped the tail curves).  2 curves x
+    65,536 Pdot values (one per lane) x 64,000 periods = 131M waves."""
+    rng = np.random.default_rng(44)
+    ts = [np.sort(rng.uniform(0, 100, 20)) for _ in range(2)]
+    ms = [rng.normal(size=20) for _ in range(2)]
+    off = np.array([0, 20, 40], dtype=np.int64)
+    periods = 1.0 / np.linspace(1.0, 30.0, 64000)
+    pdots = np.linspace(-1e-6, 1e-6, 65536)
+    w = synth.Workload("wide", np.concatenate(ts), np.concatenate(ms), off, periods,
+                       pdots, 10, 5)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(off, periods.size, pdots.size, 10, 5, trials_per_lane=1)
+    assert plan.info()["work_units"] * 64 > 2 ** 32
+    _, best = plan.execute(t, m, P, Pd)
+    torch.cuda.synchronize()
+    bf = gce.best_fields(best)
+    assert np.all(bf["flat_index"] >= 0)
+    assert np.all(bf["ce_mean"] > 0) and np.all(np.isfinite(bf["ce_std"]))
+    # the same search in two Pdot halves, merged: identical minima
+    acc, n = None, 0
+    for qa in (0, 32768):
+        p2 = gce.Plan(off, periods.size, 32768, 10, 5, trials_per_lane=1)
+        _, b2 = p2.execute(t, m, P, Pd[qa:qa + 32768].contiguous())
+        torch.cuda.synchronize()
+        acc = gce.merge_results(acc, n, b2, periods.size, 0, periods.size, qa, 32768)
+        n += periods.size * 32768
+        p2.close()
+    got = gce.best_fields(acc)
+    assert np.array_equal(got["flat_index"], bf["flat_index"])
+    # and the minimum is the CE of its trial per the oracle
+    h = oracle.trials(w.times, w.mags, off, periods, pdots, 10, 5, [0, 1],
+                      bf["flat_index"])
+    assert np.all(np.abs(h - bf["ce_min"]) <= 1e-13)
