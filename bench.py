@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="minimum only (no CE cube)")
     ap.add_argument("--trials-per-lane", type=int, default=0)
     ap.add_argument("--no-split", action="store_true", help="skip the split leg")
+    ap.add_argument("--curves", type=int, default=0,
+                    help="profiling aid: only the first CURVES curves of the workload")
     ap.add_argument("--graph", action="store_true",
                     help="time HIP-graph replays of the whole search")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -232,6 +234,8 @@ def main():
 
     dev = torch.device("cuda:0")
     w = synth.make_config(args.config)
+    if 0 < args.curves < w.n_curves:
+        w = w.subset(range(args.curves))
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     log(f"workload {WORKLOADS[args.config]}: {w.point_trials:.3g} point-trials")
     inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
@@ -260,7 +264,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.config],
+            "workload": WORKLOADS[args.config] + (
+                f" (first {w.n_curves} curves)" if 0 < args.curves else ""),
             "n_curves": w.n_curves, "points": int(w.offsets[-1]),
             "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
             "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
