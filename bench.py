@@ -41,6 +41,7 @@ WORKLOADS = {
     6: "c6: paper scale: 135 binaries x 500 epochs (~10 yr), 5,183,995 P x 32 Pdot, "
        "50x10 bins with 50% phase overlap, minimum only",
 }
+TABLES = {"auto": 0, "global": 1, "lds": 2}
 
 
 def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
@@ -108,14 +109,14 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
 
 
 def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube_on,
-              graph=False):
+              graph=False, table=0):
     """Warm up, then time exactly `steps` whole searches.  With graph=True the
     search (all four kernels) is captured once in a HIP graph and the timed
     steps are graph replays; the search kernel's own duration then comes
     from a separate eager pass with events."""
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
                     precision=precision, trials_per_lane=tq,
-                    phase_overlap=w.phase_overlap, device=dev)
+                    phase_overlap=w.phase_overlap, table_placement=table, device=dev)
     return _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph)
 
 
@@ -198,6 +199,8 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="minimum only (no CE cube)")
     ap.add_argument("--trials-per-lane", type=int, default=0)
     ap.add_argument("--no-split", action="store_true", help="skip the split leg")
+    ap.add_argument("--table", choices=["auto", "global", "lds"], default="auto",
+                    help="where the search kernel reads its c ln c table")
     ap.add_argument("--curves", type=int, default=0,
                     help="profiling aid: only the first CURVES curves of the workload")
     ap.add_argument("--graph", action="store_true",
@@ -245,7 +248,7 @@ def main():
 
     plan64, cube64, best64, el64, k64 = timed_leg(
         gce, torch, np, w, dev, inputs, 0, args.trials_per_lane, args.steps,
-        args.warmup, cube_on, args.graph)
+        args.warmup, cube_on, args.graph, TABLES[args.table])
     log(f"fp64: {el64 / args.steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
     value = pt * args.steps / el64
     bf64 = gce.best_fields(best64)
@@ -270,6 +273,7 @@ def main():
             "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
             "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
             "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
+            "table_in_lds": bool(plan64.info()["table_in_lds"]),
             "timing": "hip-graph replay" if args.graph else "eager launches",
         },
         "roofline": roofline(0, w, k64, args.config, plan64.info()["trials_per_lane"]),
@@ -304,7 +308,7 @@ def main():
     if not args.no_split:
         plan32, cube32, best32, el32, k32 = timed_leg(
             gce, torch, np, w, dev, inputs, 1, args.trials_per_lane, args.steps,
-            args.warmup, cube_on, args.graph)
+            args.warmup, cube_on, args.graph, TABLES[args.table])
         log(f"split: {el32 / args.steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
         bf32 = gce.best_fields(best32)
         strict = int(np.sum(bf32["flat_index"] == bf64["flat_index"]))
@@ -313,6 +317,7 @@ def main():
             "ms_per_step": el32 / args.steps * 1e3,
             "speedup_vs_fp64": el64 / el32,
             "trials_per_lane": plan32.info()["trials_per_lane"],
+            "table_in_lds": bool(plan32.info()["table_in_lds"]),
             "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"]),
             "best_equal_strict": f"{strict}/{w.n_curves}",
         }

@@ -119,8 +119,15 @@ typedef struct {
                                 bin k spans phases [k, k + 2) / n_phase, wrapping,
                                 so every epoch counts in two bins and the
                                 probabilities of Eq. (4) are counts / (2N) */
-    int32_t reserved;        /* must be 0 */
+    int32_t table_placement; /* c ln c table read by the entropy sums:
+                                0 = automatic, 1 = global memory, 2 = a copy in
+                                each wave's LDS (pays off when there are many
+                                histogram cells per epoch) */
 } gce_opts;
+
+#define GCE_TABLE_AUTO 0
+#define GCE_TABLE_GLOBAL 1
+#define GCE_TABLE_LDS 2
 
 /*
  * gce_plan_create -- validate the shape and the HOST offsets, build the
@@ -187,8 +194,8 @@ int gce_plan_search_times(gce_plan_t plan, float *out_ms, int32_t max,
 typedef struct {
     int32_t precision;          /* GCE_PRECISION_* */
     int32_t trials_per_lane;    /* Pdot trials per lane actually used */
-    int32_t lds_bytes_per_wave; /* histogram LDS of one search wave */
-    int32_t reserved;
+    int32_t lds_bytes_per_wave; /* LDS of one search wave */
+    int32_t table_in_lds;       /* the c ln c table is read from LDS */
     int64_t work_units;         /* waves of one search launch */
     int64_t workspace_bytes;    /* device workspace held by the plan */
 } gce_plan_info_t;
@@ -218,9 +225,10 @@ int gce_merge_results(gce_best_t *acc, int64_t acc_trials,
                       int64_t part_n_pdots);
 
 /*
- * gce_autotune -- measure the search kernel's Pdot-trials-per-lane choices
- * (1, 2, 4, 8; those whose histograms fit in LDS) on a slice of the given
- * workload and remember the fastest for its shape class: precision, phase and
+ * gce_autotune -- measure the search kernel's tilings -- Pdot trials per
+ * lane (1, 2, 4, 8) and c ln c table placement (global, LDS), those that fit
+ * in LDS -- on a slice of the given workload and remember the fastest for
+ * its shape class: precision, overlap, phase and
  * magnitude bin counts, Pdot count (1, 2, 3-4, 5-8, more) and median curve
  * length (<128, <512, <2048, more).  Later plans created with automatic tiling
  * (trials_per_lane = 0) in this process use the remembered choice.  If the
@@ -231,15 +239,18 @@ int gce_merge_results(gce_best_t *acc, int64_t acc_trials,
  * Inputs as for gce_search (times, mags, periods, pdots device; curve_offsets
  * HOST).  Allocates and synchronises `stream`; not for graph capture.
  *  best_tq  : out, the chosen trials per lane.
- *  ms       : out (may be NULL), [4] search-kernel milliseconds for 1, 2, 4,
- *             8 trials per lane; negative where a choice was not run.
+ *  best_placement : out (may be NULL), GCE_TABLE_GLOBAL or GCE_TABLE_LDS.
+ *  ms       : out (may be NULL), [8] search-kernel milliseconds for 1, 2, 4,
+ *             8 trials per lane with the table in global memory, then the
+ *             same with the table in LDS; negative where not run.
  */
 int gce_autotune(const double *times, const double *mags,
                  const int64_t *curve_offsets, int64_t n_curves,
                  const double *periods, int64_t n_periods, const double *pdots,
                  int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
-                 int32_t precision, int32_t device, void *stream,
-                 int32_t *best_tq, float *ms);
+                 int32_t precision, int32_t phase_overlap, int32_t device,
+                 void *stream, int32_t *best_tq, int32_t *best_placement,
+                 float *ms);
 
 /* Bytes of device workspace the plan holds. */
 size_t gce_plan_workspace_bytes(gce_plan_t plan);

@@ -21,13 +21,15 @@ import torch  # imported first: the library then shares torch's HIP runtime
 __all__ = [
     "GceError", "Plan", "search", "best_fields", "merge_results", "autotune", "lib",
     "LIB_PATH",
-    "PRECISION_FP64", "PRECISION_SPLIT_FP32",
+    "PRECISION_FP64", "PRECISION_SPLIT_FP32", "TABLE_AUTO", "TABLE_GLOBAL", "TABLE_LDS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgce.so")
 
 PRECISION_FP64 = 0
 PRECISION_SPLIT_FP32 = 1
+# where the search kernel reads its c ln c table from
+TABLE_AUTO, TABLE_GLOBAL, TABLE_LDS = 0, 1, 2
 
 GCE_OK = 0
 STATUS_NAMES = {0: "GCE_OK", -1: "GCE_EINVAL", -2: "GCE_ENOMEM", -3: "GCE_EHIP",
@@ -46,13 +48,13 @@ class GceError(RuntimeError):
 
 class _Info(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
-                ("lds_bytes_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lds_bytes_per_wave", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
                 ("work_units", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
-                ("phase_overlap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("phase_overlap", ctypes.c_int32), ("table_placement", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,8 +89,8 @@ def lib():
         L.gce_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
         L.gce_merge_results.argtypes = [_vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _i64]
         L.gce_autotune.argtypes = [_vp, _vp, ctypes.POINTER(_i64), _i64, _vp, _i64, _vp, _i64,
-                                   _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32),
-                                   ctypes.POINTER(ctypes.c_float)]
+                                   _i32, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32),
+                                   ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]
         L.gce_plan_search_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), _i32,
                                             ctypes.POINTER(_i32)]
         _lib = L
@@ -148,6 +150,7 @@ class Plan:
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
                  trials_per_lane: int = 0, phase_overlap: bool = False,
+                 table_placement: int = TABLE_AUTO,
                  device: Optional[torch.device] = None):
         self._h = None
         self.offsets = _host_offsets(offsets)
@@ -160,7 +163,8 @@ class Plan:
             idx = torch.cuda.current_device() if torch.cuda.is_available() else 0
             self.device = torch.device("cuda", idx)
         self.phase_overlap = bool(phase_overlap)
-        opts = _Opts(self.precision, int(trials_per_lane), int(self.phase_overlap), 0)
+        opts = _Opts(self.precision, int(trials_per_lane), int(self.phase_overlap),
+                     int(table_placement))
         h = ctypes.c_void_p()
         L = lib()
         _check(L.gce_plan_create(ctypes.byref(h),
@@ -178,7 +182,7 @@ class Plan:
         """Tiling and resources the plan chose (gce_plan_get_info)."""
         i = _Info()
         _check(lib().gce_plan_get_info(self._h, ctypes.byref(i)))
-        return {k: int(getattr(i, k)) for k, _ in _Info._fields_ if k != "reserved"}
+        return {k: int(getattr(i, k)) for k, _ in _Info._fields_}
 
     def _inputs(self, times, mags, periods, pdots):
         d = self.device
@@ -261,23 +265,26 @@ class Plan:
 
 def autotune(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Tensor,
              pdots: torch.Tensor, n_phase: int, n_mag: int,
-             precision: int = PRECISION_FP64, stream=None):
-    """Time the trials-per-lane choices on a slice of this workload and
-    remember the fastest for its shape class (gce_autotune).  Returns
-    (chosen trials per lane, {trials: kernel ms})."""
+             precision: int = PRECISION_FP64, phase_overlap: bool = False, stream=None):
+    """Time the tilings (trials per lane x table placement) on a slice of this
+    workload and remember the fastest for its shape class (gce_autotune).
+    Returns (chosen trials per lane, chosen placement,
+    {(trials, placement): kernel ms})."""
     device = times.device
     for name, x in (("times", times), ("mags", mags), ("periods", periods),
                     ("pdots", pdots)):
         _dev_f64(x, name, device)
     off = _host_offsets(offsets)
-    tq = _i32(0)
-    ms = (ctypes.c_float * 4)()
+    tq, placement = _i32(0), _i32(0)
+    ms = (ctypes.c_float * 8)()
     _check(lib().gce_autotune(_ptr(times), _ptr(mags),
                               off.ctypes.data_as(ctypes.POINTER(_i64)), off.size - 1,
                               _ptr(periods), periods.numel(), _ptr(pdots), pdots.numel(),
-                              int(n_phase), int(n_mag), int(precision), device.index or 0,
-                              _stream_handle(stream, device), ctypes.byref(tq), ms))
-    return tq.value, {t: float(v) for t, v in zip((1, 2, 4, 8), ms) if v >= 0}
+                              int(n_phase), int(n_mag), int(precision), int(phase_overlap),
+                              device.index or 0, _stream_handle(stream, device),
+                              ctypes.byref(tq), ctypes.byref(placement), ms))
+    keys = [(t, pl) for pl in (TABLE_GLOBAL, TABLE_LDS) for t in (1, 2, 4, 8)]
+    return tq.value, placement.value, {k: float(v) for k, v in zip(keys, ms) if v >= 0}
 
 
 def merge_results(acc: Optional[np.ndarray], acc_trials: int, part, n_periods: int,

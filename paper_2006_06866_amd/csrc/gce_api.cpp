@@ -75,10 +75,16 @@ int check_device(int dev)
 // ---------------------------------------------------------------------------
 // tiling choice: autotuned per shape class, else a measured heuristic
 // ---------------------------------------------------------------------------
-using TuneKey = std::tuple<int, int, int, int, int>;   // prec, nph, nmag, pd class, N class
+// prec, overlap, nph, nmag, pd class, N class
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+
+struct Tiling {
+    int tq;        // Pdot trials per lane
+    int lut_lds;   // c ln c table in LDS
+};
 
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
+std::map<TuneKey, Tiling> g_tuned;
 bool g_tune_file_read = false;
 
 int pdot_class(int64_t n_pd)
@@ -86,16 +92,29 @@ int pdot_class(int64_t n_pd)
     return n_pd <= 1 ? 0 : n_pd <= 2 ? 1 : n_pd <= 4 ? 2 : n_pd <= 8 ? 3 : 4;
 }
 
-int length_class(const int64_t *off, int64_t n_curves)
+int64_t median_length(const int64_t *off, int64_t n_curves)
 {
     std::vector<int64_t> len((size_t)n_curves);
     for (int64_t c = 0; c < n_curves; ++c) len[(size_t)c] = off[c + 1] - off[c];
     std::nth_element(len.begin(), len.begin() + n_curves / 2, len.end());
-    const int64_t med = len[(size_t)(n_curves / 2)];
+    return len[(size_t)(n_curves / 2)];
+}
+
+int length_class(const int64_t *off, int64_t n_curves)
+{
+    const int64_t med = median_length(off, n_curves);
     return med < 128 ? 0 : med < 512 ? 1 : med < 2048 ? 2 : 3;
 }
 
-// GCE_TUNE_CACHE file: one "prec nph nmag pdclass nclass tq" line per choice.
+TuneKey tune_key(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
+                 const int64_t *off, int64_t n_curves)
+{
+    return TuneKey{precision, overlap, n_phase, n_mag, pdot_class(n_pd),
+                   length_class(off, n_curves)};
+}
+
+// GCE_TUNE_CACHE file: one "prec overlap nph nmag pdclass nclass tq lut_lds"
+// line per choice.
 void read_tune_file_locked()
 {
     if (g_tune_file_read) return;
@@ -103,12 +122,23 @@ void read_tune_file_locked()
     const char *path = std::getenv("GCE_TUNE_CACHE");
     if (!path || !*path) return;
     std::ifstream in(path);
-    int a, b, c, d, e, tq;
-    while (in >> a >> b >> c >> d >> e >> tq)
-        if (tq == 1 || tq == 2 || tq == 4 || tq == 8) g_tuned[TuneKey{a, b, c, d, e}] = tq;
+    int a, b, c, d, e, f, tq, ll;
+    while (in >> a >> b >> c >> d >> e >> f >> tq >> ll)
+        if ((tq == 1 || tq == 2 || tq == 4 || tq == 8) && (ll == 0 || ll == 1))
+            g_tuned[TuneKey{a, b, c, d, e, f}] = Tiling{tq, ll};
 }
 
-int heuristic_tq(int precision, int n_phase, int64_t n_pd)
+// The table in LDS costs every wave one pass over max_n + 1 doubles and
+// LDS space, and saves a global gather per histogram cell at every
+// magnitude-segment flush: it pays when the table is small and the cells
+// are many per epoch.
+int heuristic_lut_lds(int n_phase, int n_mag, int32_t max_n, int64_t median_n)
+{
+    return (max_n + 1) * 8 <= 8 * 1024 &&
+           4 * (int64_t)n_phase * n_mag >= median_n;
+}
+
+int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
 {
     // Pdot trials per lane: more trials share each point's x and x^2, but
     // every trial pair adds a histogram region of LDS.  Measured on MI355X:
@@ -117,26 +147,39 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd)
     // at 20 KiB (20 bins) the CU holds too few waves and 4 trials wins
     // (64 x 5,000 x 100,000 x 256: 1.25 s at 4 vs 1.70 s at 8).
     int tq = 8;
-    while (tq > 1 && (tq >= 2 * n_pd ||
-                      !gce::search_variant_exists(precision, n_phase, tq) ||
-                      gce::search_lds_bytes(precision, n_phase, tq) > 13 * 1024))
+    while (tq > 1 &&
+           (tq >= 2 * n_pd || !gce::search_variant_exists(precision, n_phase, tq) ||
+            gce::search_lds_bytes(precision, n_phase, tq, 0, max_n) > 13 * 1024))
         tq /= 2;
     return tq;
 }
 
-int choose_tq(int precision, int n_phase, int n_mag, int64_t n_pd, const int64_t *off,
-              int64_t n_curves, int requested)
+// Tiling of a plan: an explicit request wins, then an autotuned choice for
+// the shape class, then the heuristics.  A tuned trials-per-lane count is
+// used only with the table placement it was measured with.
+Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
+                     const int64_t *off, int64_t n_curves, int32_t max_n,
+                     int requested_tq, int requested_placement)
 {
-    if (requested > 0) return requested;
+    Tiling tuned{0, 0};
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         read_tune_file_locked();
-        auto it = g_tuned.find(TuneKey{precision, n_phase, n_mag, pdot_class(n_pd),
-                                       length_class(off, n_curves)});
-        if (it != g_tuned.end() && gce::search_variant_exists(precision, n_phase, it->second))
-            return it->second;
+        auto it = g_tuned.find(tune_key(precision, overlap, n_phase, n_mag, n_pd, off,
+                                        n_curves));
+        if (it != g_tuned.end() &&
+            gce::search_variant_exists(precision, n_phase, it->second.tq))
+            tuned = it->second;
     }
-    return heuristic_tq(precision, n_phase, n_pd);
+    Tiling t{0, 0};
+    if (requested_placement == GCE_TABLE_GLOBAL) t.lut_lds = 0;
+    else if (requested_placement == GCE_TABLE_LDS) t.lut_lds = 1;
+    else if (tuned.tq > 0) t.lut_lds = tuned.lut_lds;
+    else t.lut_lds = heuristic_lut_lds(n_phase, n_mag, max_n, median_length(off, n_curves));
+    if (requested_tq > 0) t.tq = requested_tq;
+    else if (tuned.tq > 0 && tuned.lut_lds == t.lut_lds) t.tq = tuned.tq;
+    else t.tq = heuristic_tq(precision, n_phase, n_pd, max_n);
+    return t;
 }
 
 }  // namespace
@@ -245,15 +288,23 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     if (o.trials_per_lane != 0 && o.trials_per_lane != 1 && o.trials_per_lane != 2 &&
         o.trials_per_lane != 4 && o.trials_per_lane != 8)
         return fail(GCE_EINVAL, "trials_per_lane must be 0, 1, 2, 4 or 8");
-    if (o.reserved != 0) return fail(GCE_EINVAL, "reserved option field must be 0");
     if (o.phase_overlap != 0 && o.phase_overlap != 1)
         return fail(GCE_EINVAL, "phase_overlap must be 0 or 1");
-    const int tq = choose_tq(o.precision, n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
-                             n_curves, o.trials_per_lane);
+    if (o.table_placement != GCE_TABLE_AUTO && o.table_placement != GCE_TABLE_GLOBAL &&
+        o.table_placement != GCE_TABLE_LDS)
+        return fail(GCE_EINVAL, "table_placement must be 0, 1 or 2");
+    const Tiling tl = choose_tiling(o.precision, o.phase_overlap, n_phase_bins, n_mag_bins,
+                                    n_pdots, curve_offsets, n_curves, max_n,
+                                    o.trials_per_lane, o.table_placement);
+    const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
-    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq) > 64 * 1024)
-        return fail(GCE_EUNSUPPORTED, "histograms exceed 64 KiB of LDS: lower trials_per_lane");
+    if (tl.lut_lds && max_n > 8191)   // LDS-table counts are kept in units of 8
+        return fail(GCE_EUNSUPPORTED, "the table in LDS needs curves of at most 8191 epochs");
+    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_n) > 64 * 1024)
+        return fail(GCE_EUNSUPPORTED,
+                    "a wave's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
+                    "table in global memory");
 
     rc = check_device(device);
     if (rc != GCE_OK) return rc;
@@ -282,6 +333,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.max_n = max_n;
     dp.precision = o.precision;
     dp.overlap = o.phase_overlap;
+    dp.lut_lds = tl.lut_lds;
     if (dp.n_units > gce::kMaxUnits) {
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
@@ -466,9 +518,9 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
     if (!pl || !info) return fail(GCE_EINVAL, "NULL argument");
     info->precision = pl->dp.precision;
     info->trials_per_lane = pl->dp.tq;
-    info->lds_bytes_per_wave =
-        (int32_t)gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq);
-    info->reserved = 0;
+    info->lds_bytes_per_wave = (int32_t)gce::search_lds_bytes(
+        pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds, pl->dp.max_n);
+    info->table_in_lds = pl->dp.lut_lds;
     info->work_units = pl->dp.n_units;
     info->workspace_bytes = (int64_t)pl->ws_bytes;
     return GCE_OK;
@@ -615,8 +667,9 @@ extern "C" int gce_autotune(const double *times, const double *mags,
                             const double *periods, int64_t n_periods,
                             const double *pdots, int64_t n_pdots,
                             int32_t n_phase_bins, int32_t n_mag_bins,
-                            int32_t precision, int32_t device, void *stream,
-                            int32_t *best_tq, float *ms)
+                            int32_t precision, int32_t phase_overlap, int32_t device,
+                            void *stream, int32_t *best_tq, int32_t *best_placement,
+                            float *ms)
 {
     int32_t max_n = 0;
     int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots, n_phase_bins,
@@ -626,6 +679,8 @@ extern "C" int gce_autotune(const double *times, const double *mags,
         return fail(GCE_EINVAL, "NULL pointer");
     if (precision != GCE_PRECISION_FP64 && precision != GCE_PRECISION_SPLIT_FP32)
         return fail(GCE_EINVAL, "unknown precision");
+    if (phase_overlap != 0 && phase_overlap != 1)
+        return fail(GCE_EINVAL, "phase_overlap must be 0 or 1");
     rc = check_device(device);
     if (rc != GCE_OK) return rc;
     DeviceGuard guard(device);
@@ -667,17 +722,19 @@ extern "C" int gce_autotune(const double *times, const double *mags,
     }
     const int cands[4] = {1, 2, 4, 8};
     float best_ms = -1.f;
-    int chosen = 0;
-    for (int ci = 0; ci < 4 && e == hipSuccess; ++ci) {
+    Tiling chosen{0, 0};
+    for (int ci = 0; ci < 8 && e == hipSuccess; ++ci) {
         if (ms) ms[ci] = -1.f;
-        const int tq = cands[ci];
+        const int tq = cands[ci % 4], ll = ci / 4;
         if (tq > 1 && tq >= 2 * n_pdots) continue;
         if (!gce::search_variant_exists(precision, n_phase_bins, tq) ||
-            gce::search_lds_bytes(precision, n_phase_bins, tq) > 40 * 1024)
+            gce::search_lds_bytes(precision, n_phase_bins, tq, ll, max_n) > 40 * 1024)
             continue;
         gce_opts o{};
         o.precision = precision;
         o.trials_per_lane = tq;
+        o.phase_overlap = phase_overlap;
+        o.table_placement = ll ? GCE_TABLE_LDS : GCE_TABLE_GLOBAL;
         gce_plan_t pl = nullptr;
         rc = gce_plan_create(&pl, off.data(), k, np_slice, n_pdots, n_phase_bins,
                              n_mag_bins, &o, device);
@@ -701,7 +758,7 @@ extern "C" int gce_autotune(const double *times, const double *mags,
         if (ms) ms[ci] = t;
         if (best_ms < 0.f || t < best_ms) {
             best_ms = t;
-            chosen = tq;
+            chosen = Tiling{tq, ll};
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -709,19 +766,21 @@ extern "C" int gce_autotune(const double *times, const double *mags,
     if (buf) (void)hipFree(buf);
     if (best) (void)hipFree(best);
     if (e != hipSuccess) return fail_hip(e, "autotune");
-    if (chosen == 0) return fail(GCE_EUNSUPPORTED, "no tiling fits this shape");
-    *best_tq = chosen;
-    const TuneKey key{precision, n_phase_bins, n_mag_bins, pdot_class(n_pdots),
-                      length_class(curve_offsets, n_curves)};
+    if (chosen.tq == 0) return fail(GCE_EUNSUPPORTED, "no tiling fits this shape");
+    *best_tq = chosen.tq;
+    if (best_placement) *best_placement = chosen.lut_lds ? GCE_TABLE_LDS : GCE_TABLE_GLOBAL;
+    const TuneKey key = tune_key(precision, phase_overlap, n_phase_bins, n_mag_bins, n_pdots,
+                                 curve_offsets, n_curves);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     read_tune_file_locked();
     g_tuned[key] = chosen;
     if (const char *path = std::getenv("GCE_TUNE_CACHE")) {
         if (*path) {
             std::ofstream out(path, std::ios::app);
-            out << precision << ' ' << n_phase_bins << ' ' << n_mag_bins << ' '
-                << pdot_class(n_pdots) << ' ' << length_class(curve_offsets, n_curves)
-                << ' ' << chosen << '\n';
+            out << precision << ' ' << phase_overlap << ' ' << n_phase_bins << ' '
+                << n_mag_bins << ' ' << pdot_class(n_pdots) << ' '
+                << length_class(curve_offsets, n_curves) << ' ' << chosen.tq << ' '
+                << chosen.lut_lds << '\n';
         }
     }
     return GCE_OK;

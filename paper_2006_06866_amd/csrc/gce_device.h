@@ -1,0 +1,167 @@
+// gce_device.h -- device helpers shared by the search, prepass, epilogue
+// and debug kernels (Katz et al. 2020, Sec. 2.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "gce_internal.h"
+
+// Tuning of the search kernel's epoch loop (measured on MI355X).
+#ifndef GCE_UNROLL_SMALL_TQ
+#define GCE_UNROLL_SMALL_TQ 8   // epochs per iteration, trials_per_lane <= 4
+#endif
+#ifndef GCE_UNROLL_LARGE_TQ
+#define GCE_UNROLL_LARGE_TQ 4   // epochs per iteration, trials_per_lane = 8
+#endif
+#ifndef GCE_PREFETCH
+#define GCE_PREFETCH 0          // load the next epochs during the current ones
+#endif
+#ifndef GCE_SCALAR_EPOCHS
+#define GCE_SCALAR_EPOCHS 1     // read epoch offsets with scalar loads
+#endif
+#ifndef GCE_WAVES_PER_EU
+#define GCE_WAVES_PER_EU 0      // occupancy hint for the search kernel (0: none)
+#endif
+#if GCE_WAVES_PER_EU > 0
+#define GCE_SEARCH_ATTR __attribute__((amdgpu_waves_per_eu(GCE_WAVES_PER_EU)))
+#else
+#define GCE_SEARCH_ATTR
+#endif
+namespace gce {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+// Read-only, wave-uniform arrays (a curve's epoch offsets and segment
+// starts) are read through the constant address space, so the loads become
+// scalar loads into SGPRs that the vector instructions take as operands.
+#if GCE_SCALAR_EPOCHS
+typedef __attribute__((address_space(4))) const double uniform_f64;
+typedef __attribute__((address_space(4))) const int32_t uniform_i32;
+#else
+typedef const double uniform_f64;
+typedef const int32_t uniform_i32;
+#endif
+
+__device__ __forceinline__ uint32_t lds_add(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Eq. (3) phase bin in binary64, bit-identical to the documented sequence
+// y = fma(-Pdot/2, x^2, x); phi = y - floor(y); bin = (int)(phi * n_phase).
+// v_fract_f64 returns y - floor(y) clamped to 1 - 2^-53; the clamp maps a
+// phase that rounds up to 1 into the last bin, as the reference clamp does,
+// and (1 - 2^-53) * n < n for every bin count n, so no clamp is needed.
+__device__ __forceinline__ int fp64_phase_bin(double x, double x2,
+                                              double half_pdot, double nph)
+{
+    const double y = __builtin_fma(-half_pdot, x2, x);
+    const double fr = __builtin_amdgcn_fract(y);
+    return (int)(fr * nph);
+}
+
+__device__ __forceinline__ bool lex_less(double h1, int64_t f1, double h2,
+                                         int64_t f2)
+{
+    // NaN never wins; among equal values the lower flat index wins.
+    if (f2 < 0) return f1 >= 0;
+    if (f1 < 0) return false;
+    return (h1 < h2) || (h1 == h2 && f1 < f2);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Chan et al. pairwise update of (count, mean, M2) with another part.
+__device__ __forceinline__ void moments_merge(double &n, double &mean, double &m2,
+                                              double nb, double mb, double m2b)
+{
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb;
+        mean = mb;
+        m2 = m2b;
+        return;
+    }
+    const double nn = n + nb;
+    const double d = mb - mean;
+    mean += d * (nb / nn);
+    m2 += m2b + d * d * (n * nb / nn);
+    n = nn;
+}
+
+__device__ __forceinline__ void wave_argmin(double &h, int64_t &f)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ho = __shfl_xor(h, off, kWave);
+        const int64_t fo = __shfl_xor(f, off, kWave);
+        if (lex_less(ho, fo, h, f)) {
+            h = ho;
+            f = fo;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// split-precision binning
+// ---------------------------------------------------------------------------
+// Split-precision bin.  FP64 forms the point-period part x = dt / P, x^2 and
+// frac(x) - 1/(2n) (the phase shifted down by half a bin); FP32 applies each
+// trial's Pdot term, reduces mod 1 and rounds n * phase to the nearest
+// integer by adding 1.5 * 2^23 (the float's low mantissa bits then hold the
+// integer).  round(n * frac(y - 1/(2n))) equals floor(n * frac(y)), except
+// that the upper half of bin 0 rounds to n: slot n is a wrap slot folded into
+// bin 0 at each flush.  The shift is 2^-23 cycle short of half a bin: a phase
+// exactly on a bin edge (every curve's first epoch has phase 0 for every
+// trial) would otherwise be an exact rounding tie decided by the float
+// rounding of 1/(2n); with the margin exact edges fall in the right bin, and
+// only phases within 2^-23 cycle below an edge move up.  Accuracy is that of
+// the FP32 Pdot term (~1e-7 of its size) and of frac(x) rounded to float
+// (2^-25 cycle).
+constexpr float kRoundMagic = 12582912.0f;           // 1.5 * 2^23
+constexpr uint32_t kRoundMagicBits = 0x4B400000u;    // its bit pattern
+
+__device__ __forceinline__ double split_shift(int nph)
+{
+    return 0.5 / (double)nph - 0x1p-23;
+}
+
+struct SplitPoint {
+    float xf;    // frac(x) - 1/(2n)
+    float x2f;   // x^2
+};
+
+__device__ __forceinline__ SplitPoint split_point(double dt, double invp,
+                                                  double half_bin)
+{
+    const double x = dt * invp;
+    SplitPoint sp;
+    sp.xf = (float)(__builtin_amdgcn_fract(x) - half_bin);
+    sp.x2f = (float)(x * x);
+    return sp;
+}
+
+// Bit pattern kRoundMagicBits + slot, slot in [0, n] (n = wrap slot).
+__device__ __forceinline__ uint32_t split_slot_bits(SplitPoint sp, float half_pdot,
+                                                    float nph)
+{
+    const float y = __builtin_fmaf(-half_pdot, sp.x2f, sp.xf);
+    const float fr = __builtin_amdgcn_fractf(y);
+    return __float_as_uint(__builtin_fmaf(fr, nph, kRoundMagic));
+}
+
+constexpr int kPrecFp64 = GCE_PRECISION_FP64;
+constexpr int kPrecSplit = GCE_PRECISION_SPLIT_FP32;
+
+}  // namespace gce

@@ -54,6 +54,7 @@ struct DevPlan {
     int32_t max_n;            // longest curve
     int32_t precision;
     int32_t overlap;          // 50%-overlapping phase bins
+    int32_t lut_lds;          // c ln c table copied into LDS by each wave
 
     // plan-time metadata
     const int64_t *off;       // [n_curves + 1] curve offsets
@@ -86,9 +87,28 @@ hipError_t launch_debug_counts(const DevPlan &dp, const int64_t *trial_curve,
                                const int64_t *trial_flat, int64_t n_trials,
                                uint32_t *out_counts, hipStream_t s);
 
+// Search-kernel variants of one precision and phase-bin kind, each table
+// compiled in its own translation unit (gce_search_*.hip).
+using SearchFn = void (*)(DevPlan, void *);
+struct SearchVariant {
+    int32_t nph;   // phase bins fixed at compile time; 0 = any count
+    int32_t tq;    // Pdot trials per lane
+    int32_t ll;    // c ln c table in LDS
+    SearchFn fn;
+};
+struct SearchTable {
+    const SearchVariant *v;
+    int32_t n;
+};
+SearchTable search_table_fp64();
+SearchTable search_table_fp64_overlap();
+SearchTable search_table_split();
+SearchTable search_table_split_overlap();
+
 // Search-kernel variants compiled into the library.
 bool search_variant_exists(int precision, int n_phase, int tq);
-// Bytes of LDS one search wave uses.
-size_t search_lds_bytes(int precision, int n_phase, int tq);
+// Bytes of LDS one search wave uses (lut_lds: the c ln c table of max_n + 1
+// entries is kept in LDS too).
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_n);
 
 }  // namespace gce

@@ -5,122 +5,12 @@
 //   k_grid_setup  1/P and Pdot/2 per grid value, grid validity      (trial setup)
 //   k_prepass     per curve: t0, magnitude bins, points grouped by
 //                 magnitude bin (stable counting sort)               (prepass)
-//   k_search_*    the fold of Eq. (3), 2-D histogram, Eq. (4)        (hot loop)
+//   k_search      the fold of Eq. (3), 2-D histogram, Eq. (4)        (hot loop,
+//                 gce_search.h, instantiated by gce_search_*.hip)
 //   k_epilogue    per-curve minimum over the work units              (argmin)
-//
-// Search-kernel layout (one wave = one work unit):
-//   lane l          <-> period index p = 64 * tile + l
-//   trial t < TQ    <-> Pdot index q = TQ * group + t (same for the wave)
-//   epoch k         <-> uniform across the wave: dt_k is read with scalar
-//                       loads and enters the VALU as an SGPR operand.
-// Epochs are pre-grouped by magnitude bin, so each lane only keeps a 1-D
-// phase histogram per trial (the paper's Sec. 2.3 GPU observation that one
-// magnitude value's phase counts suffice); at the end of each magnitude
-// segment the histogram is folded into the entropy sums and cleared.
-// Histograms live in LDS as [trial pair][phase bin][lane] 32-bit words: the
-// low and high 16 bits count trials 2r and 2r+1, so one ds_add_u32 with
-// value 1 or 0x10000 bins one point-trial, and lanes always hit distinct
-// banks.  The marginal phase counts accumulate in registers.
-//
-// Entropy: N * H = sum_b c_b ln c_b - sum_{j,b} c_jb ln c_jb, which equals
-// Eq. (4) multiplied by N; c ln c comes from a table built on the device.
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdint>
-#include <type_traits>
-
-#include "gce_internal.h"
-
-// Tuning of the search kernel's epoch loop (measured on MI355X).
-#ifndef GCE_UNROLL_SMALL_TQ
-#define GCE_UNROLL_SMALL_TQ 8   // epochs per iteration, trials_per_lane <= 4
-#endif
-#ifndef GCE_UNROLL_LARGE_TQ
-#define GCE_UNROLL_LARGE_TQ 4   // epochs per iteration, trials_per_lane = 8
-#endif
-#ifndef GCE_PREFETCH
-#define GCE_PREFETCH 0          // load the next epochs during the current ones
-#endif
-#ifndef GCE_WAVES_PER_EU
-#define GCE_WAVES_PER_EU 0      // occupancy hint for the search kernel (0: none)
-#endif
-#if GCE_WAVES_PER_EU > 0
-#define GCE_SEARCH_ATTR __attribute__((amdgpu_waves_per_eu(GCE_WAVES_PER_EU)))
-#else
-#define GCE_SEARCH_ATTR
-#endif
+#include "gce_device.h"
 
 namespace gce {
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t lds_add(uint32_t *p, uint32_t v)
-{
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-
-// Eq. (3) phase bin in binary64, bit-identical to the documented sequence
-// y = fma(-Pdot/2, x^2, x); phi = y - floor(y); bin = (int)(phi * n_phase).
-// v_fract_f64 returns y - floor(y) clamped to 1 - 2^-53; the clamp maps a
-// phase that rounds up to 1 into the last bin, as the reference clamp does,
-// and (1 - 2^-53) * n < n for every bin count n, so no clamp is needed.
-__device__ __forceinline__ int fp64_phase_bin(double x, double x2,
-                                              double half_pdot, double nph)
-{
-    const double y = __builtin_fma(-half_pdot, x2, x);
-    const double fr = __builtin_amdgcn_fract(y);
-    return (int)(fr * nph);
-}
-
-__device__ __forceinline__ bool lex_less(double h1, int64_t f1, double h2,
-                                         int64_t f2)
-{
-    // NaN never wins; among equal values the lower flat index wins.
-    if (f2 < 0) return f1 >= 0;
-    if (f1 < 0) return false;
-    return (h1 < h2) || (h1 == h2 && f1 < f2);
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-// Chan et al. pairwise update of (count, mean, M2) with another part.
-__device__ __forceinline__ void moments_merge(double &n, double &mean, double &m2,
-                                              double nb, double mb, double m2b)
-{
-    if (nb == 0.0) return;
-    if (n == 0.0) {
-        n = nb;
-        mean = mb;
-        m2 = m2b;
-        return;
-    }
-    const double nn = n + nb;
-    const double d = mb - mean;
-    mean += d * (nb / nn);
-    m2 += m2b + d * d * (n * nb / nn);
-    n = nn;
-}
-
-__device__ __forceinline__ void wave_argmin(double &h, int64_t &f)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ho = __shfl_xor(h, off, kWave);
-        const int64_t fo = __shfl_xor(f, off, kWave);
-        if (lex_less(ho, fo, h, f)) {
-            h = ho;
-            f = fo;
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // c ln c table
@@ -306,391 +196,47 @@ hipError_t launch_prepass(const DevPlan &dp, const double *times,
 }
 
 // ---------------------------------------------------------------------------
-// search kernel (FP64 and split precision)
+// search-kernel dispatch
 // ---------------------------------------------------------------------------
-// Split-precision bin.  FP64 forms the point-period part x = dt / P, x^2 and
-// frac(x) - 1/(2n) (the phase shifted down by half a bin); FP32 applies each
-// trial's Pdot term, reduces mod 1 and rounds n * phase to the nearest
-// integer by adding 1.5 * 2^23 (the float's low mantissa bits then hold the
-// integer).  round(n * frac(y - 1/(2n))) equals floor(n * frac(y)), except
-// that the upper half of bin 0 rounds to n: slot n is a wrap slot folded into
-// bin 0 at each flush.  The shift is 2^-23 cycle short of half a bin: a phase
-// exactly on a bin edge (every curve's first epoch has phase 0 for every
-// trial) would otherwise be an exact rounding tie decided by the float
-// rounding of 1/(2n); with the margin exact edges fall in the right bin, and
-// only phases within 2^-23 cycle below an edge move up.  Accuracy is that of
-// the FP32 Pdot term (~1e-7 of its size) and of frac(x) rounded to float
-// (2^-25 cycle).
-constexpr float kRoundMagic = 12582912.0f;           // 1.5 * 2^23
-constexpr uint32_t kRoundMagicBits = 0x4B400000u;    // its bit pattern
-
-__device__ __forceinline__ double split_shift(int nph)
+static SearchTable search_table(int precision, int overlap)
 {
-    return 0.5 / (double)nph - 0x1p-23;
+    if (precision == kPrecFp64) return overlap ? search_table_fp64_overlap() : search_table_fp64();
+    return overlap ? search_table_split_overlap() : search_table_split();
 }
 
-struct SplitPoint {
-    float xf;    // frac(x) - 1/(2n)
-    float x2f;   // x^2
-};
-
-__device__ __forceinline__ SplitPoint split_point(double dt, double invp,
-                                                  double half_bin)
+static const SearchVariant *find_variant(int prec, int overlap, int n_phase, int tq, int ll)
 {
-    const double x = dt * invp;
-    SplitPoint sp;
-    sp.xf = (float)(__builtin_amdgcn_fract(x) - half_bin);
-    sp.x2f = (float)(x * x);
-    return sp;
-}
-
-// Bit pattern kRoundMagicBits + slot, slot in [0, n] (n = wrap slot).
-__device__ __forceinline__ uint32_t split_slot_bits(SplitPoint sp, float half_pdot,
-                                                    float nph)
-{
-    const float y = __builtin_fmaf(-half_pdot, sp.x2f, sp.xf);
-    const float fr = __builtin_amdgcn_fractf(y);
-    return __float_as_uint(__builtin_fmaf(fr, nph, kRoundMagic));
-}
-
-constexpr int kPrecFp64 = GCE_PRECISION_FP64;
-constexpr int kPrecSplit = GCE_PRECISION_SPLIT_FP32;
-
-// NPH > 0: phase-bin count fixed at compile time, marginals in VGPRs.
-// NPH = 0: runtime phase-bin count, marginals in LDS behind the histograms.
-template <int PREC, int NPH, int TQ>
-struct SearchShape {
-    static constexpr int kRegions = (TQ + 1) / 2;
-    static constexpr bool kLdsMarg = (NPH == 0);
-    static constexpr int kWrap = (PREC == kPrecSplit) ? 1 : 0;   // extra slot
-    // phase bins per scheduling group of the segment flush: ~8 words,
-    // i.e. ~16 table loads, in flight at a time
-    static constexpr int kFlushGroup = kRegions >= 8 ? 1 : 8 / kRegions;
-};
-
-template <int PREC, int NPH, int TQ>
-__global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
-                                                                  void *out_ce_v)
-{
-    using S = SearchShape<PREC, NPH, TQ>;
-    using OutT = typename std::conditional<PREC == kPrecFp64, double, float>::type;
-    constexpr int R = S::kRegions;
-    extern __shared__ uint32_t lds[];
-    OutT *__restrict__ out_ce = static_cast<OutT *>(out_ce_v);
-
-    const int lane = threadIdx.x;
-    const int nph = NPH > 0 ? NPH : dp.n_phase;
-    const int nslot = nph + S::kWrap;                   // LDS words per region
-    // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
-    // unit = y * gridDim.x + x, in dispatch order
-    const int64_t u = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (u >= dp.n_units) return;
-    const int64_t rank = u / dp.units_per_curve;
-    const int64_t rem = u - rank * dp.units_per_curve;
-    const int32_t g = (int32_t)(rem / dp.n_ptiles);
-    const int64_t tile = rem - (int64_t)g * dp.n_ptiles;
-    const int32_t c = dp.order[rank];
-    const int64_t base = dp.off[c];
-    const int32_t n = (int32_t)(dp.off[c + 1] - base);
-    const int64_t p = tile * kWave + lane;
-    const bool p_ok = p < dp.n_p;
-    const int32_t q0 = g * TQ;
-
-    if (!(dp.curve_ok[c] && *dp.grid_ok)) {
-        if (out_ce && p_ok) {
-#pragma unroll
-            for (int t = 0; t < TQ; ++t)
-                if (q0 + t < dp.n_pd)
-                    out_ce[((int64_t)c * dp.n_pd + q0 + t) * dp.n_p + p] = (OutT)NAN;
-        }
-        if (lane == 0) {
-            dp.partials[u] = Partial{NAN, -1};
-            dp.stats[u] = UnitStats{0.0, 0.0, 0.0};
-        }
-        return;
-    }
-
-    const double invp = dp.inv_p[p_ok ? p : dp.n_p - 1];
-    double ha[TQ];
-    float ha32[TQ];
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) {
-        const int32_t q = min(q0 + t, (int32_t)dp.n_pd - 1);
-        if constexpr (PREC == kPrecFp64) ha[t] = dp.half_pd[q];
-        else ha32[t] = dp.half_pd32[q];
-    }
-
-    uint32_t *hist = lds;                                  // [R][nslot][64]
-    uint32_t *lmarg = lds + (size_t)R * nslot * kWave;     // [R][nph][64] (NPH == 0)
-    for (int i = 0; i < R * nslot; ++i) hist[i * kWave + lane] = 0;
-    if (S::kLdsMarg)
-        for (int i = 0; i < R * nph; ++i) lmarg[i * kWave + lane] = 0;
-    uint32_t vmarg[R][NPH > 0 ? NPH : 1];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int b = 0; b < (NPH > 0 ? NPH : 1); ++b) vmarg[r][b] = 0;
-
-    double s1[TQ];
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) s1[t] = 0.0;
-
-    const double nphd = (double)nph;
-    const float nphf = (float)nph;
-    const double half_bin = split_shift(nph);
-    // split path: (bits << 8) of slot s is 0x40000000 + 256 s (mod 2^32)
-    const uint32_t split_base = (uint32_t)lane * 4u - (kRoundMagicBits << 8);
-    const double *__restrict__ dts = dp.dt_sorted + base;
-    const int32_t *segc = dp.seg + (int64_t)c * (dp.n_mag + 1);
-    const double *__restrict__ lut = dp.lut;
-    uint32_t *hcol = hist + lane;
-    char *lbytes = reinterpret_cast<char *>(lds);
-
-    auto fold_point = [&](double dt) {
-        if constexpr (PREC == kPrecFp64) {
-            const double x = dt * invp;
-            const double x2 = x * x;
-#pragma unroll
-            for (int t = 0; t < TQ; ++t) {
-                const int b = fp64_phase_bin(x, x2, ha[t], nphd);
-                lds_add(hcol + ((t >> 1) * nslot + b) * kWave,
-                        (t & 1) ? 0x10000u : 1u);
-            }
-        } else {
-            const SplitPoint sp = split_point(dt, invp, half_bin);
-#pragma unroll
-            for (int t = 0; t < TQ; ++t) {
-                const uint32_t bits = split_slot_bits(sp, ha32[t], nphf);
-                const uint32_t addr = (bits << 8) + split_base +
-                                      (uint32_t)((t >> 1) * nslot * kWave * 4);
-                lds_add(reinterpret_cast<uint32_t *>(lbytes + addr),
-                        (t & 1) ? 0x10000u : 1u);
-            }
-        }
-    };
-
-    // end of a magnitude segment: sum c ln c, add to marginals, clear
-    auto cell = [&](int r, int b) -> uint32_t * { return hcol + (r * nslot + b) * kWave; };
-    auto add_lut = [&](int r, uint32_t w) {
-        s1[2 * r] += lut[w & 0xffffu];
-        if (2 * r + 1 < TQ) s1[2 * r + 1] += lut[w >> 16];
-    };
-    // One branch-free pass over the phase bins.  With 50%-overlapping bins,
-    // bin b spans disjoint bins b and b + 1 (mod n): its count is the sum of
-    // the two words (packed halves cannot overflow: together they hold at
-    // most the curve's N epochs); with disjoint bins the neighbour is masked
-    // to zero.  Bin 0's word (wrap slot merged) is kept in a register for
-    // the last bin, so every cell is cleared as soon as it is read.
-    const bool ovl = dp.overlap != 0;
-    const uint32_t nb_mask = ovl ? 0xffffffffu : 0u;
-    auto flush_segment = [&]() {
-        uint32_t w0[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            w0[r] = *cell(r, 0);
-            if (S::kWrap) {   // the wrap slot belongs to bin 0
-                w0[r] += *cell(r, nph);
-                *cell(r, nph) = 0;
-            }
-        }
-        if constexpr (NPH > 0) {
-#pragma unroll
-            for (int b = 0; b < NPH; ++b) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
-                    const uint32_t wn = ((b + 1 < NPH) ? *cell(r, b + 1) : w0[r]) & nb_mask;
-                    *cell(r, b) = 0;
-                    vmarg[r][b] += w;
-                    add_lut(r, w + wn);
-                }
-                // bound the table loads in flight (register pressure): no
-                // memory access may move across this point
-                if ((b + 1) % S::kFlushGroup == 0) asm volatile("" ::: "memory");
-            }
-        } else {
-            for (int b = 0; b < nph; ++b) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
-                    const uint32_t wn = ((b + 1 < nph) ? *cell(r, b + 1) : w0[r]) & nb_mask;
-                    *cell(r, b) = 0;
-                    lmarg[(r * nph + b) * kWave + lane] += w;
-                    add_lut(r, w + wn);
-                }
-            }
-        }
-    };
-
-    for (int32_t j = 0; j < dp.n_mag; ++j) {
-        const int32_t k0 = segc[j], k1 = segc[j + 1];
-        if (k0 == k1) continue;
-        // U epochs per iteration; optionally the next U epoch offsets are
-        // loaded while the current ones are binned.
-        constexpr int U = (TQ >= 8) ? GCE_UNROLL_LARGE_TQ : GCE_UNROLL_SMALL_TQ;
-        int32_t k = k0;
-        if (k + U <= k1) {
-            double cur[U], nxt[U];
-#pragma unroll
-            for (int uu = 0; uu < U; ++uu) cur[uu] = dts[k + uu];
-            while (true) {
-                const int32_t kn = k + U;
-                const bool more = kn + U <= k1;
-                if (GCE_PREFETCH && more) {
-#pragma unroll
-                    for (int uu = 0; uu < U; ++uu) nxt[uu] = dts[kn + uu];
-                }
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu) fold_point(cur[uu]);
-                k = kn;
-                if (!more) break;
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu)
-                    cur[uu] = GCE_PREFETCH ? nxt[uu] : dts[k + uu];
-            }
-        }
-        for (; k < k1; ++k) fold_point(dts[k]);
-
-        flush_segment();
-    }
-
-    double s2[TQ];
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) s2[t] = 0.0;
-    auto marg_word = [&](int r, uint32_t w) {
-        s2[2 * r] += lut[w & 0xffffu];
-        if (2 * r + 1 < TQ) s2[2 * r + 1] += lut[w >> 16];
-    };
-    if constexpr (NPH > 0) {
-        // the histograms are empty now: park the register marginals there and
-        // sum them in a rolled loop (an unrolled one keeps every table load
-        // in flight at once)
-#pragma unroll
-        for (int b = 0; b < NPH; ++b)
-#pragma unroll
-            for (int r = 0; r < R; ++r) hcol[(r * nslot + b) * kWave] = vmarg[r][b];
-#pragma unroll 1
-        for (int b = 0; b < NPH; ++b) {
-            const int bn = (b + 1 == NPH) ? 0 : b + 1;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                marg_word(r, hcol[(r * nslot + b) * kWave] +
-                                 (hcol[(r * nslot + bn) * kWave] & nb_mask));
-        }
-    } else {
-        for (int b = 0; b < nph; ++b) {
-            const int bn = (b + 1 == nph) ? 0 : b + 1;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                marg_word(r, lmarg[(r * nph + b) * kWave + lane] +
-                                 (lmarg[(r * nph + bn) * kWave + lane] & nb_mask));
-        }
-    }
-
-    // probabilities are counts / N, or counts / (2N) with overlapping bins
-    const double nd = ovl ? 2.0 * (double)n : (double)n;
-    double best_h = NAN;
-    int64_t best_f = -1;
-    double hv[TQ];
-    double lsum = 0.0, lcnt = 0.0;
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) {
-        const OutT h = (OutT)((s2[t] - s1[t]) / nd);
-        hv[t] = (double)h;
-        const int32_t q = q0 + t;
-        if (p_ok && q < dp.n_pd) {
-            const int64_t flat = (int64_t)q * dp.n_p + p;
-            if (out_ce) out_ce[((int64_t)c * dp.n_pd + q) * dp.n_p + p] = h;
-            if (lex_less(hv[t], flat, best_h, best_f)) {
-                best_h = hv[t];
-                best_f = flat;
-            }
-            lsum += hv[t];
-            lcnt += 1.0;
-        }
-    }
-    wave_argmin(best_h, best_f);
-    // moments of this unit's CE values (two passes over registers)
-    const double wcnt = wave_sum(lcnt);
-    const double wmean = wave_sum(lsum) / wcnt;
-    double lm2 = 0.0;
-#pragma unroll
-    for (int t = 0; t < TQ; ++t)
-        if (p_ok && q0 + t < dp.n_pd) {
-            const double d = hv[t] - wmean;
-            lm2 += d * d;
-        }
-    const double wm2 = wave_sum(lm2);
-    if (lane == 0) {
-        dp.partials[u] = Partial{best_h, best_f};
-        dp.stats[u] = UnitStats{wcnt, wmean, wm2};
-    }
-}
-
-// ---------------------------------------------------------------------------
-// variant table
-// ---------------------------------------------------------------------------
-using SearchFn = void (*)(DevPlan, void *);
-
-struct Variant {
-    int prec;
-    int nph;   // 0 = generic
-    int tq;
-    SearchFn fn;
-};
-
-#define GCE_V(P, N, T) Variant{P, N, T, &k_search<P, N, T>}
-static const Variant kVariants[] = {
-    GCE_V(kPrecFp64, 10, 1), GCE_V(kPrecFp64, 10, 2), GCE_V(kPrecFp64, 10, 4),
-    GCE_V(kPrecFp64, 10, 8),
-    GCE_V(kPrecFp64, 15, 1), GCE_V(kPrecFp64, 15, 2), GCE_V(kPrecFp64, 15, 4),
-    GCE_V(kPrecFp64, 15, 8),
-    GCE_V(kPrecFp64, 20, 1), GCE_V(kPrecFp64, 20, 2), GCE_V(kPrecFp64, 20, 4),
-    GCE_V(kPrecFp64, 20, 8),
-    GCE_V(kPrecFp64, 50, 1), GCE_V(kPrecFp64, 50, 2), GCE_V(kPrecFp64, 50, 4),
-    GCE_V(kPrecFp64, 0, 1),  GCE_V(kPrecFp64, 0, 2),  GCE_V(kPrecFp64, 0, 4),
-    GCE_V(kPrecFp64, 0, 8),
-    GCE_V(kPrecSplit, 10, 1), GCE_V(kPrecSplit, 10, 2), GCE_V(kPrecSplit, 10, 4),
-    GCE_V(kPrecSplit, 10, 8),
-    GCE_V(kPrecSplit, 15, 1), GCE_V(kPrecSplit, 15, 2), GCE_V(kPrecSplit, 15, 4),
-    GCE_V(kPrecSplit, 15, 8),
-    GCE_V(kPrecSplit, 20, 1), GCE_V(kPrecSplit, 20, 2), GCE_V(kPrecSplit, 20, 4),
-    GCE_V(kPrecSplit, 20, 8),
-    GCE_V(kPrecSplit, 50, 1), GCE_V(kPrecSplit, 50, 2), GCE_V(kPrecSplit, 50, 4),
-    GCE_V(kPrecSplit, 0, 1),  GCE_V(kPrecSplit, 0, 2),  GCE_V(kPrecSplit, 0, 4),
-    GCE_V(kPrecSplit, 0, 8),
-};
-#undef GCE_V
-
-static const Variant *find_variant(int prec, int n_phase, int tq)
-{
-    for (const Variant &v : kVariants)
-        if (v.prec == prec && v.nph == n_phase && v.tq == tq) return &v;
-    for (const Variant &v : kVariants)
-        if (v.prec == prec && v.nph == 0 && v.tq == tq) return &v;
+    const SearchTable t = search_table(prec, overlap);
+    for (int32_t i = 0; i < t.n; ++i)
+        if (t.v[i].nph == n_phase && t.v[i].tq == tq && t.v[i].ll == ll) return &t.v[i];
+    for (int32_t i = 0; i < t.n; ++i)
+        if (t.v[i].nph == 0 && t.v[i].tq == tq && t.v[i].ll == ll) return &t.v[i];
     return nullptr;
 }
 
 bool search_variant_exists(int precision, int n_phase, int tq)
 {
-    return find_variant(precision, n_phase, tq) != nullptr;
+    return find_variant(precision, 0, n_phase, tq, 0) != nullptr;
 }
 
-size_t search_lds_bytes(int precision, int n_phase, int tq)
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_n)
 {
-    const Variant *v = find_variant(precision, n_phase, tq);
+    const SearchVariant *v = find_variant(precision, 0, n_phase, tq, 0);
     const size_t regions = (size_t)(tq + 1) / 2;
     const size_t slots = (size_t)n_phase + (precision == kPrecSplit ? 1 : 0);
     const size_t hist = regions * slots * kWave * sizeof(uint32_t);
     const size_t marg = regions * (size_t)n_phase * kWave * sizeof(uint32_t);
-    return (v && v->nph == 0) ? hist + marg : hist;
+    size_t bytes = (v && v->nph == 0) ? hist + marg : hist;
+    if (lut_lds) bytes = ((bytes + 7) & ~(size_t)7) + sizeof(double) * (size_t)(max_n + 1);
+    return bytes;
 }
 
 hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
 {
-    const Variant *v = find_variant(dp.precision, dp.n_phase, dp.tq);
+    const SearchVariant *v =
+        find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds);
     if (!v) return hipErrorInvalidValue;
-    const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq);
+    const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_n);
     const int64_t gx = dp.n_units < kSearchGridX ? dp.n_units : kSearchGridX;
     const int64_t gy = (dp.n_units + gx - 1) / gx;
     hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave), lds, s,

@@ -1,0 +1,353 @@
+// gce_search.h -- the search kernel template: the fold of Eq. (3), the
+// per-lane phase histograms and the entropy of Eq. (4) (Katz et al. 2020,
+// Sec. 2.3).  Instantiated by the gce_search_*.hip files, one per precision
+// and phase-bin kind, so the variants compile in parallel.
+//
+// Search-kernel layout (one wave = one work unit):
+//   lane l          <-> period index p = 64 * tile + l
+//   trial t < TQ    <-> Pdot index q = TQ * group + t (same for the wave)
+//   epoch k         <-> uniform across the wave: dt_k is read with scalar
+//                       loads and enters the VALU as an SGPR operand.
+// Epochs are pre-grouped by magnitude bin, so each lane only keeps a 1-D
+// phase histogram per trial (the paper's Sec. 2.3 GPU observation that one
+// magnitude value's phase counts suffice); at the end of each magnitude
+// segment the histogram is folded into the entropy sums and cleared.
+// Histograms live in LDS as [trial pair][phase bin][lane] 32-bit words: the
+// low and high 16 bits count trials 2r and 2r+1, so one ds_add_u32 bins one
+// point-trial, and lanes always hit distinct banks.  The marginal phase
+// counts accumulate in registers.
+//
+// Entropy: N * H = sum_b c_b ln c_b - sum_{j,b} c_jb ln c_jb, which equals
+// Eq. (4) multiplied by N; c ln c comes from a table built on the device.
+#pragma once
+
+#include "gce_device.h"
+
+namespace gce {
+
+// NPH > 0: phase-bin count fixed at compile time, marginals in VGPRs.
+// NPH = 0: runtime phase-bin count, marginals in LDS behind the histograms.
+template <int PREC, int NPH, int TQ>
+struct SearchShape {
+    static constexpr int kRegions = (TQ + 1) / 2;
+    static constexpr bool kLdsMarg = (NPH == 0);
+    static constexpr int kWrap = (PREC == kPrecSplit) ? 1 : 0;   // extra slot
+    // phase bins per scheduling group of the segment flush: ~8 words,
+    // i.e. ~16 table loads, in flight at a time
+    static constexpr int kFlushGroup = kRegions >= 8 ? 1 : 8 / kRegions;
+};
+
+// LL = 1: the c ln c table is copied into LDS behind the histograms (for
+// shapes with many cells per epoch, where the segment flush dominates).
+// OVL = 1: 50%-overlapping phase bins (each epoch counts in two bins).
+template <int PREC, int NPH, int TQ, int LL, int OVL>
+__global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
+                                                                  void *out_ce_v)
+{
+    using S = SearchShape<PREC, NPH, TQ>;
+    using OutT = typename std::conditional<PREC == kPrecFp64, double, float>::type;
+    constexpr int R = S::kRegions;
+    extern __shared__ uint32_t lds[];
+    OutT *__restrict__ out_ce = static_cast<OutT *>(out_ce_v);
+
+    const int lane = threadIdx.x;
+    const int nph = NPH > 0 ? NPH : dp.n_phase;
+    const int nslot = nph + S::kWrap;                   // LDS words per region
+    // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
+    // unit = y * gridDim.x + x, in dispatch order
+    const int64_t u = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (u >= dp.n_units) return;
+    const int64_t rank = u / dp.units_per_curve;
+    const int64_t rem = u - rank * dp.units_per_curve;
+    const int32_t g = (int32_t)(rem / dp.n_ptiles);
+    const int64_t tile = rem - (int64_t)g * dp.n_ptiles;
+    const int32_t c = dp.order[rank];
+    const int64_t base = dp.off[c];
+    const int32_t n = (int32_t)(dp.off[c + 1] - base);
+    const int64_t p = tile * kWave + lane;
+    const bool p_ok = p < dp.n_p;
+    const int32_t q0 = g * TQ;
+
+    if (!(dp.curve_ok[c] && *dp.grid_ok)) {
+        if (out_ce && p_ok) {
+#pragma unroll
+            for (int t = 0; t < TQ; ++t)
+                if (q0 + t < dp.n_pd)
+                    out_ce[((int64_t)c * dp.n_pd + q0 + t) * dp.n_p + p] = (OutT)NAN;
+        }
+        if (lane == 0) {
+            dp.partials[u] = Partial{NAN, -1};
+            dp.stats[u] = UnitStats{0.0, 0.0, 0.0};
+        }
+        return;
+    }
+
+    const double invp = dp.inv_p[p_ok ? p : dp.n_p - 1];
+    double ha[TQ];
+    float ha32[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+        const int32_t q = min(q0 + t, (int32_t)dp.n_pd - 1);
+        if constexpr (PREC == kPrecFp64) ha[t] = dp.half_pd[q];
+        else ha32[t] = dp.half_pd32[q];
+    }
+
+    uint32_t *hist = lds;                                  // [R][nslot][64]
+    uint32_t *lmarg = lds + (size_t)R * nslot * kWave;     // [R][nph][64] (NPH == 0)
+    // LDS copy of the c ln c table, 8-byte aligned, after the count words
+    double *lut_lds = reinterpret_cast<double *>(
+        lds + (((size_t)R * (nslot + (S::kLdsMarg ? nph : 0)) * kWave + 1) & ~(size_t)1));
+    if (LL) {
+        for (int c = lane; c <= dp.max_n; c += kWave) lut_lds[c] = dp.lut[c];
+        __syncthreads();
+    }
+    for (int i = 0; i < R * nslot; ++i) hist[i * kWave + lane] = 0;
+    if (S::kLdsMarg)
+        for (int i = 0; i < R * nph; ++i) lmarg[i * kWave + lane] = 0;
+    uint32_t vmarg[R][NPH > 0 ? NPH : 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int b = 0; b < (NPH > 0 ? NPH : 1); ++b) vmarg[r][b] = 0;
+
+    double s1[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) s1[t] = 0.0;
+
+    const double nphd = (double)nph;
+    const float nphf = (float)nph;
+    const double half_bin = split_shift(nph);
+    // split path: (bits << 8) of slot s is 0x40000000 + 256 s (mod 2^32)
+    const uint32_t split_base = (uint32_t)lane * 4u - (kRoundMagicBits << 8);
+    uniform_f64 *dts = (uniform_f64 *)(dp.dt_sorted + base);
+    uniform_i32 *segc = (uniform_i32 *)(dp.seg + (int64_t)c * (dp.n_mag + 1));
+    const double *__restrict__ lut = LL ? lut_lds : dp.lut;
+    uint32_t *hcol = hist + lane;
+    char *lbytes = reinterpret_cast<char *>(lds);
+
+    // With the table in LDS (LL), counts are kept in units of 8 (at most
+    // 8 * 8191 per 16-bit half), so a half is directly the byte offset of
+    // its c ln c entry: no shift before each table load.
+    constexpr uint32_t kUnit = LL ? 8u : 1u;
+    const uint32_t inc_lo = kUnit, inc_hi = kUnit << 16;
+    auto fold_point = [&](double dt) {
+        if constexpr (PREC == kPrecFp64) {
+            const double x = dt * invp;
+            const double x2 = x * x;
+#pragma unroll
+            for (int t = 0; t < TQ; ++t) {
+                const int b = fp64_phase_bin(x, x2, ha[t], nphd);
+                lds_add(hcol + ((t >> 1) * nslot + b) * kWave, (t & 1) ? inc_hi : inc_lo);
+            }
+        } else {
+            const SplitPoint sp = split_point(dt, invp, half_bin);
+#pragma unroll
+            for (int t = 0; t < TQ; ++t) {
+                const uint32_t bits = split_slot_bits(sp, ha32[t], nphf);
+                const uint32_t addr = (bits << 8) + split_base +
+                                      (uint32_t)((t >> 1) * nslot * kWave * 4);
+                lds_add(reinterpret_cast<uint32_t *>(lbytes + addr),
+                        (t & 1) ? inc_hi : inc_lo);
+            }
+        }
+    };
+
+    // c ln c of the two counts packed in a word
+    auto lut_lo = [&](uint32_t w) -> double {
+        if constexpr (LL)
+            return *reinterpret_cast<const double *>(
+                reinterpret_cast<const char *>(lut) + (w & 0xffffu));
+        else
+            return lut[w & 0xffffu];
+    };
+    auto lut_hi = [&](uint32_t w) -> double {
+        if constexpr (LL)
+            return *reinterpret_cast<const double *>(
+                reinterpret_cast<const char *>(lut) + (w >> 16));
+        else
+            return lut[w >> 16];
+    };
+
+    // end of a magnitude segment: sum c ln c, add to marginals, clear
+    auto cell = [&](int r, int b) -> uint32_t * { return hcol + (r * nslot + b) * kWave; };
+    auto add_lut = [&](int r, uint32_t w) {
+        s1[2 * r] += lut_lo(w);
+        if (2 * r + 1 < TQ) s1[2 * r + 1] += lut_hi(w);
+    };
+    // One pass over the phase bins.  With 50%-overlapping bins, bin b
+    // spans disjoint bins b and b + 1 (mod n): its count is the sum of the
+    // two words (packed halves cannot overflow: together they hold at most
+    // the curve's N epochs).  Bin 0's word (wrap slot merged) is kept in a
+    // register for the last bin, so every cell is cleared as soon as it is
+    // read.
+    auto flush_segment = [&]() {
+        uint32_t w0[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w0[r] = *cell(r, 0);
+            if (S::kWrap) {   // the wrap slot belongs to bin 0
+                w0[r] += *cell(r, nph);
+                *cell(r, nph) = 0;
+            }
+        }
+        if constexpr (NPH > 0) {
+#pragma unroll
+            for (int b = 0; b < NPH; ++b) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
+                    uint32_t wo = w;
+                    if constexpr (OVL) wo += (b + 1 < NPH) ? *cell(r, b + 1) : w0[r];
+                    *cell(r, b) = 0;
+                    vmarg[r][b] += w;
+                    add_lut(r, wo);
+                }
+                // bound the table loads in flight (register pressure): no
+                // memory access may move across this point
+                if ((b + 1) % S::kFlushGroup == 0) asm volatile("" ::: "memory");
+            }
+        } else {
+            for (int b = 0; b < nph; ++b) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t w = (b == 0) ? w0[r] : *cell(r, b);
+                    uint32_t wo = w;
+                    if constexpr (OVL) wo += (b + 1 < nph) ? *cell(r, b + 1) : w0[r];
+                    *cell(r, b) = 0;
+                    lmarg[(r * nph + b) * kWave + lane] += w;
+                    add_lut(r, wo);
+                }
+            }
+        }
+    };
+
+    for (int32_t j = 0; j < dp.n_mag; ++j) {
+        const int32_t k0 = segc[j], k1 = segc[j + 1];
+        if (k0 == k1) continue;
+        // U epochs per iteration; optionally the next U epoch offsets are
+        // loaded while the current ones are binned.
+        constexpr int U = (TQ >= 8) ? GCE_UNROLL_LARGE_TQ : GCE_UNROLL_SMALL_TQ;
+        int32_t k = k0;
+        if (k + U <= k1) {
+            double cur[U], nxt[U];
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu) cur[uu] = dts[k + uu];
+            while (true) {
+                const int32_t kn = k + U;
+                const bool more = kn + U <= k1;
+                if (GCE_PREFETCH && more) {
+#pragma unroll
+                    for (int uu = 0; uu < U; ++uu) nxt[uu] = dts[kn + uu];
+                }
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) fold_point(cur[uu]);
+                k = kn;
+                if (!more) break;
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu)
+                    cur[uu] = GCE_PREFETCH ? nxt[uu] : dts[k + uu];
+            }
+        }
+        for (; k < k1; ++k) fold_point(dts[k]);
+
+        flush_segment();
+    }
+
+    double s2[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) s2[t] = 0.0;
+    auto marg_word = [&](int r, uint32_t w) {
+        s2[2 * r] += lut_lo(w);
+        if (2 * r + 1 < TQ) s2[2 * r + 1] += lut_hi(w);
+    };
+    constexpr uint32_t nb_mask = OVL ? 0xffffffffu : 0u;
+    if constexpr (NPH > 0) {
+        // the histograms are empty now: park the register marginals there and
+        // sum them in a rolled loop (an unrolled one keeps every table load
+        // in flight at once)
+#pragma unroll
+        for (int b = 0; b < NPH; ++b)
+#pragma unroll
+            for (int r = 0; r < R; ++r) hcol[(r * nslot + b) * kWave] = vmarg[r][b];
+#pragma unroll 1
+        for (int b = 0; b < NPH; ++b) {
+            const int bn = (b + 1 == NPH) ? 0 : b + 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                marg_word(r, hcol[(r * nslot + b) * kWave] +
+                                 (hcol[(r * nslot + bn) * kWave] & nb_mask));
+        }
+    } else {
+        for (int b = 0; b < nph; ++b) {
+            const int bn = (b + 1 == nph) ? 0 : b + 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                marg_word(r, lmarg[(r * nph + b) * kWave + lane] +
+                                 (lmarg[(r * nph + bn) * kWave + lane] & nb_mask));
+        }
+    }
+
+    // probabilities are counts / N, or counts / (2N) with overlapping bins
+    const double nd = OVL ? 2.0 * (double)n : (double)n;
+    double best_h = NAN;
+    int64_t best_f = -1;
+    double hv[TQ];
+    double lsum = 0.0, lcnt = 0.0;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+        const OutT h = (OutT)((s2[t] - s1[t]) / nd);
+        hv[t] = (double)h;
+        const int32_t q = q0 + t;
+        if (p_ok && q < dp.n_pd) {
+            const int64_t flat = (int64_t)q * dp.n_p + p;
+            if (out_ce) out_ce[((int64_t)c * dp.n_pd + q) * dp.n_p + p] = h;
+            if (lex_less(hv[t], flat, best_h, best_f)) {
+                best_h = hv[t];
+                best_f = flat;
+            }
+            lsum += hv[t];
+            lcnt += 1.0;
+        }
+    }
+    wave_argmin(best_h, best_f);
+    // moments of this unit's CE values (two passes over registers)
+    const double wcnt = wave_sum(lcnt);
+    const double wmean = wave_sum(lsum) / wcnt;
+    double lm2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t)
+        if (p_ok && q0 + t < dp.n_pd) {
+            const double d = hv[t] - wmean;
+            lm2 += d * d;
+        }
+    const double wm2 = wave_sum(lm2);
+    if (lane == 0) {
+        dp.partials[u] = Partial{best_h, best_f};
+        dp.stats[u] = UnitStats{wcnt, wmean, wm2};
+    }
+}
+
+// Table of the variants of one precision and phase-bin kind: every
+// compiled phase-bin count (0 = any count), trials per lane and table
+// placement.  Expanded once in each gce_search_*.hip file.
+#define GCE_SV(P, O, N, T)                                                      \
+    SearchVariant{N, T, 0, &k_search<P, N, T, 0, O>},                           \
+        SearchVariant{N, T, 1, &k_search<P, N, T, 1, O>}
+#define GCE_SEARCH_TABLE(P, O, FN)                                              \
+    namespace gce {                                                             \
+    static const SearchVariant kSearchTable[] = {                               \
+        GCE_SV(P, O, 10, 1), GCE_SV(P, O, 10, 2), GCE_SV(P, O, 10, 4),          \
+        GCE_SV(P, O, 10, 8), GCE_SV(P, O, 15, 1), GCE_SV(P, O, 15, 2),          \
+        GCE_SV(P, O, 15, 4), GCE_SV(P, O, 15, 8), GCE_SV(P, O, 20, 1),          \
+        GCE_SV(P, O, 20, 2), GCE_SV(P, O, 20, 4), GCE_SV(P, O, 20, 8),          \
+        GCE_SV(P, O, 50, 1), GCE_SV(P, O, 50, 2), GCE_SV(P, O, 50, 4),          \
+        GCE_SV(P, O, 0, 1),  GCE_SV(P, O, 0, 2),  GCE_SV(P, O, 0, 4),           \
+        GCE_SV(P, O, 0, 8)};                                                    \
+    SearchTable FN()                                                            \
+    {                                                                           \
+        return SearchTable{kSearchTable,                                        \
+                           (int32_t)(sizeof(kSearchTable) / sizeof(kSearchTable[0]))}; \
+    }                                                                           \
+    }
+
+}  // namespace gce

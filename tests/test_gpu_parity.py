@@ -20,12 +20,15 @@ pytestmark = pytest.mark.gpu
 
 
 def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0,
-                 phase_overlap=False):
+                 phase_overlap=False, table_placement=0):
     say(f"[parity] {label}: curves={w.n_curves} N={w.lengths.tolist()[:8]} "
         f"n_p={w.periods.size} n_pd={w.pdots.size} bins={w.n_phase}x{w.n_mag} "
-        f"tq={trials_per_lane} overlap={phase_overlap}")
+        f"tq={trials_per_lane} overlap={phase_overlap} table={table_placement}")
     plan, dev, cube, best = run_gpu(w, trials_per_lane=trials_per_lane,
-                                    phase_overlap=phase_overlap)
+                                    phase_overlap=phase_overlap,
+                                    table_placement=table_placement)
+    if table_placement:
+        assert plan.info()["table_in_lds"] == int(table_placement == gce.TABLE_LDS)
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
                                  w.n_phase, w.n_mag, phase_overlap=phase_overlap)
     gc = cube.cpu().numpy()
@@ -82,6 +85,37 @@ def test_ragged_small_grid(n_phase, n_mag, tq):
     w = synth.random_curves(20 + n_phase + 7 * tq, EDGE_LENGTHS, n_freq=150,
                             n_pdots=7, n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
     _full_parity(w, f"ragged nph={n_phase} nmag={n_mag}", trials_per_lane=tq)
+
+
+@pytest.mark.parametrize("placement", [gce.TABLE_GLOBAL, gce.TABLE_LDS])
+@pytest.mark.parametrize("n_phase,n_mag,tq", [
+    (10, 5, 8), (50, 10, 4), (7, 3, 1), (20, 10, 2), (1, 1, 0),
+])
+def test_table_placement(n_phase, n_mag, tq, placement):
+    """The c ln c table read from global memory or from a copy in each
+    wave's LDS gives the same counts and CE values (curves up to 1,000
+    epochs: the copy loop runs over several 64-lane strides and a tail)."""
+    w = synth.random_curves(60 + n_phase + tq, EDGE_LENGTHS, n_freq=140,
+                            n_pdots=5, n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
+    _full_parity(w, f"table={placement} nph={n_phase}", trials_per_lane=tq,
+                 table_placement=placement)
+    _full_parity(w, f"table={placement} overlap nph={n_phase}", trials_per_lane=tq,
+                 table_placement=placement, phase_overlap=True)
+
+
+@pytest.mark.parametrize("precision", [gce.PRECISION_FP64, gce.PRECISION_SPLIT_FP32])
+def test_table_placement_bitwise_equal(precision):
+    """Both placements hold the same doubles and sum them in the same order,
+    so every CE value and every minimum agrees bit for bit."""
+    w = synth.random_curves(77, [1, 64, 65, 500, 1000], n_freq=200, n_pdots=9,
+                            n_phase=50, n_mag=10, pdot_scale=5e-9)
+    out = []
+    for placement in (gce.TABLE_GLOBAL, gce.TABLE_LDS):
+        plan, _, cube, best = run_gpu(w, precision=precision, table_placement=placement)
+        out.append((cube, best))
+        plan.close()
+    assert torch.equal(out[0][0].view(torch.int32), out[1][0].view(torch.int32))
+    assert torch.equal(out[0][1].view(torch.int64), out[1][1].view(torch.int64))
 
 
 def test_single_pdot_and_single_period():
@@ -291,11 +325,14 @@ def test_overlap_rejects_nothing_and_differs_from_disjoint():
 def test_autotune_picks_a_measured_tiling():
     w = synth.make_config(2).subset(np.arange(64))
     t, m, P, Pd = upload(w)
-    tq, ms = gce.autotune(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag)
-    say(f"[autotune] chose {tq}: {ms}")
-    assert tq in ms and ms[tq] == min(ms.values())
+    tq, placement, ms = gce.autotune(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag)
+    say(f"[autotune] chose {tq}, table {placement}: {ms}")
+    assert (tq, placement) in ms and ms[(tq, placement)] == min(ms.values())
+    assert any(k[1] == gce.TABLE_LDS for k in ms) and any(k[1] == gce.TABLE_GLOBAL for k in ms)
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
-    assert plan.info()["trials_per_lane"] == tq
+    info = plan.info()
+    assert info["trials_per_lane"] == tq
+    assert info["table_in_lds"] == int(placement == gce.TABLE_LDS)
 
 
 def test_search_beyond_32bit_dispatch_grid():
