@@ -153,18 +153,29 @@ def _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph):
     return plan, cube, best, elapsed, float(np.mean(kernel_ms)) / 1e3
 
 
+SEARCH_SOURCES = ("gce_search.h", "gce_device.h")
+
+
+def search_source_sha256():
+    """sha256 over the search kernel's sources (the template and its device
+    helpers), which the committed counter summaries are tied to."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SEARCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2006_06866_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(config, precision):
     """HBM bytes per search launch from the committed rocprofv3 counter
     summary, or None when the kernel source has changed since it was taken
     or the workload differs."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_search_c{config}_traffic.json")
-    src = os.path.join(ROOT, "paper_2006_06866_amd", "csrc", "gce_kernels.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = search_source_sha256()
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != sha:

@@ -91,3 +91,22 @@ def check_counts_exact(plan, dev_inputs, w, curve_ids, flat_ids, label=""):
                              f"gpu={got[i].tolist()}\noracle={want[i].tolist()}")
     mult = 2 if ovl else 1
     assert np.all(got.sum(axis=(1, 2)) == mult * w.lengths[np.asarray(curve_ids)])
+
+
+def best_rows(cube):
+    """gce_best_t rows ([n_curves, 6] float64 words) of a [n_curves, n_pd, n_p]
+    CE array: first minimum in flat order, population mean and std, rho."""
+    nc = cube.shape[0]
+    out = np.zeros((nc, gce.BEST_WORDS))
+    raw = out.view(np.uint8).reshape(nc, 8 * gce.BEST_WORDS)
+    for c in range(nc):
+        flat = cube[c].ravel()
+        f = int(np.argmin(flat))
+        q, p = divmod(f, cube.shape[2])
+        mu, sd = flat.mean(), flat.std()
+        raw[c, 0:8] = np.array([f], dtype=np.int64).view(np.uint8)
+        raw[c, 8:16] = np.array([p, q], dtype=np.int32).view(np.uint8)
+        raw[c, 16:48] = np.array([flat[f], mu, sd, (mu - flat[f]) / sd if sd > 0 else 0.0]
+                                 ).view(np.uint8)
+    return out
+

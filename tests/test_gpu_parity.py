@@ -370,3 +370,64 @@ def test_search_beyond_32bit_dispatch_grid():
     h = oracle.trials(w.times, w.mags, off, periods, pdots, 10, 5, [0, 1],
                       bf["flat_index"])
     assert np.all(np.abs(h - bf["ce_min"]) <= 1e-13)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_chunked_search_matches_one_launch(tmp_path, overlap):
+    """Period-range chunks merged on the host (with a checkpoint, and a
+    resume after an interruption) give the one-launch minimum exactly and
+    its statistics to rounding."""
+    from paper_2006_06866_amd import chunked
+    w = synth.random_curves(120 + overlap, [64, 300, 1000], n_freq=900, n_pdots=6,
+                            n_phase=20, n_mag=5, pdot_scale=5e-9)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
+                    phase_overlap=overlap)
+    _, best = plan.execute(t, m, P, Pd)
+    torch.cuda.synchronize()
+    want = gce.best_fields(best)
+    plan.close()
+    ck = str(tmp_path / "c.npz")
+    seen = []
+
+    class Stop(Exception):
+        pass
+
+    def stop_after_two(i, p0, p1, cube):
+        seen.append((p0, p1))
+        if len(seen) == 2:
+            raise Stop
+
+    with pytest.raises(Stop):
+        chunked.search_chunked(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, 256,
+                               checkpoint=ck, phase_overlap=overlap, on_range=stop_after_two)
+    # the interrupted range ran but its callback raised before the save
+    assert chunked.load_checkpoint(ck, chunked.fingerprint(
+        [w.offsets, w.times, w.mags, w.periods, w.pdots], n_phase=w.n_phase,
+        n_mag=w.n_mag, precision=0, phase_overlap=overlap, chunk=256))[1] == 1
+    seen.clear()
+    acc = chunked.search_chunked(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, 256,
+                                 checkpoint=ck, phase_overlap=overlap,
+                                 on_range=lambda i, p0, p1, c: seen.append((p0, p1)))
+    assert seen == [(256, 512), (512, 768), (768, 900)]
+    got = gce.best_fields(acc)
+    for k in ("flat_index", "period_index", "pdot_index", "ce_min"):
+        assert np.array_equal(got[k], want[k]), k
+    assert np.allclose(got["ce_mean"], want["ce_mean"], rtol=0, atol=1e-13)
+    assert np.allclose(got["ce_std"], want["ce_std"], rtol=1e-9, atol=1e-14)
+
+
+def test_automatic_table_placement():
+    """The automatic choice keeps the table in global memory for dense
+    histograms, long curves or large LDS, and moves it to LDS for many cells
+    per epoch (the paper-scale shape: 50 x 10 bins, ~500 epochs)."""
+    def info(lengths, n_phase, n_mag, overlap=False, n_pd=32):
+        off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+        p = gce.Plan(off, 1000, n_pd, n_phase, n_mag, phase_overlap=overlap)
+        i = p.info()
+        p.close()
+        return i
+    assert info([600] * 4, 10, 5)["table_in_lds"] == 0          # dense: c2-like
+    assert info([500] * 4, 50, 10, True)["table_in_lds"] == 1   # paper scale
+    assert info([3000] * 4, 50, 10)["table_in_lds"] == 0        # table over 8 KiB
+    assert info([100] * 4, 128, 5, n_pd=1)["table_in_lds"] == 0  # LDS budget

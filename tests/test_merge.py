@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import paper_2006_06866_amd as gce
+from gce_testlib import best_rows as _result
 from paper_2006_06866_amd import build as gbuild
 import os
 
@@ -13,23 +14,6 @@ import os
 def _ensure_built():
     if not os.path.exists(gce.LIB_PATH):
         gbuild.build()
-
-
-def _result(cube):
-    """gce_best_t rows of a [n_curves, n_pd, n_p] CE array."""
-    nc = cube.shape[0]
-    out = np.zeros((nc, gce.BEST_WORDS))
-    raw = out.view(np.uint8).reshape(nc, 8 * gce.BEST_WORDS)
-    for c in range(nc):
-        flat = cube[c].ravel()
-        f = int(np.argmin(flat))
-        q, p = divmod(f, cube.shape[2])
-        mu, sd = flat.mean(), flat.std()
-        raw[c, 0:8] = np.array([f], dtype=np.int64).view(np.uint8)
-        raw[c, 8:16] = np.array([p, q], dtype=np.int32).view(np.uint8)
-        raw[c, 16:48] = np.array([flat[f], mu, sd, (mu - flat[f]) / sd if sd > 0 else 0.0]
-                                 ).view(np.uint8)
-    return out
 
 
 @pytest.mark.parametrize("split_axis", ["pdot", "period", "both"])
