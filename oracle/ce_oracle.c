@@ -19,6 +19,8 @@
  *     [0, 1] by their min and max and cut into n_mag equal-width bins; the
  *     median/std scaling of Sec. 2.3 is affine and so leaves these bins alone;
  *   - right edges (m = m_max, phase rounding up to 1) fall in the last bin;
+ *   - the phase bin is floor(phi * n_phase) of the exact product (the
+ *     computed phase phi itself is the rounded fold of Eq. (3));
  *   - empty histogram cells contribute nothing to Eq. (4);
  *   - the minimum over the grid is the first strict minimum in flat order
  *     flat = q * n_periods + p (Pdot index q outer, period index p inner);
@@ -72,13 +74,33 @@ int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
 }
 
 /* ---------------------------------------------------------------------------
+ * Sec. 2.3: n_phase equal-width phase bins; phase phi lies in bin
+ * floor(phi * n_phase).  The floor is taken of the exact product: phi * n is
+ * split into its rounded value p and the exact remainder e = phi*n - p (one
+ * fused multiply-add, the error-free product of Ogita, Rump and Oishi 2005),
+ * and a product that rounds up onto an integer is moved back below it.  A
+ * phase that rounds up to 1 falls in the last bin.
+ * ------------------------------------------------------------------------- */
+static int32_t phase_bin(double phi, int32_t n_phase)
+{
+    double n = (double)n_phase;
+    double p = phi * n;
+    double f = floor(p);
+    /* floor(p) is the exact floor unless p rounded up onto an integer */
+    if (f == p && fma(phi, n, -p) < 0.0)   /* phi * n == p + remainder */
+        f -= 1.0;
+    int32_t b = (int32_t)f;
+    if (b >= n_phase) b = n_phase - 1;
+    return b;
+}
+
+/* ---------------------------------------------------------------------------
  * Eq. (3): the quadratic phase fold.  With x = dt / P the folded phase is
  *     phi = frac( x - (1/2) * Pdot * x^2 ),
  * which is Eq. (3) divided through by P.  1/P is taken once per trial by a
  * correctly rounded division; (1/2)*Pdot is exact.  The square of x is formed
  * first and the Pdot term is applied with one fused multiply-add.
- * Returns the phase bin in [0, n_phase); a phase that rounds up to 1 falls in
- * the last bin.
+ * Returns the phase bin in [0, n_phase).
  * ------------------------------------------------------------------------- */
 static int32_t fold_bin(double dt, double inv_p, double half_pdot,
                         int32_t n_phase)
@@ -87,9 +109,7 @@ static int32_t fold_bin(double dt, double inv_p, double half_pdot,
     double x2 = x * x;
     double y = fma(-half_pdot, x2, x);
     double phi = y - floor(y);
-    int32_t b = (int32_t)(phi * (double)n_phase);
-    if (b >= n_phase) b = n_phase - 1;
-    return b;
+    return phase_bin(phi, n_phase);
 }
 
 /* The classic P-only fold (Pdot absent): phi = frac(dt / P). */
@@ -97,9 +117,7 @@ static int32_t fold_bin_ponly(double dt, double inv_p, int32_t n_phase)
 {
     double y = dt * inv_p;
     double phi = y - floor(y);
-    int32_t b = (int32_t)(phi * (double)n_phase);
-    if (b >= n_phase) b = n_phase - 1;
-    return b;
+    return phase_bin(phi, n_phase);
 }
 
 /* Exposed for the exact-arithmetic fold tests. */

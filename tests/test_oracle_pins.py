@@ -85,6 +85,33 @@ def test_fold_matches_exact_rationals_on_dyadic_inputs():
         assert oracle.fold_bin(dt, P, Pd, n) == _exact_bin(dt, P, Pd, n)
 
 
+def test_phase_bin_is_floor_of_exact_product():
+    """Sec. 2.3 bins: phase phi lies in bin floor(phi * n) of the exact
+    product.  Adversarial phases sit on and next to every bin edge k/n (the
+    rounded k/n, and its neighbours one ulp away), where the rounded product
+    phi * n lands on the integer k although the exact one is below it (e.g.
+    fl(1/3) * 3 rounds to 1, fl(0.3) * 10 to 3).  dt = phi, P = 1, Pdot = 0
+    makes the fold return phi unchanged."""
+    rng = np.random.default_rng(11)
+    phis = set(float(v) for v in rng.uniform(0, 1, 300))
+    for n in (1, 2, 3, 5, 7, 10, 20, 33, 50, 100, 127, 128):
+        for k in range(0, n + 1):
+            e = k / n
+            for v in (e, math.nextafter(e, 0.0), math.nextafter(e, 1.0)):
+                if 0.0 <= v < 1.0:
+                    phis.add(v)
+    phis.add(math.nextafter(1.0, 0.0))
+    rounded_up = 0
+    for n in (1, 2, 3, 5, 7, 10, 20, 33, 50, 100, 127, 128):
+        for phi in phis:
+            want = min(math.floor(Fraction(phi) * n), n - 1)
+            assert oracle.fold_bin(phi, 1.0, 0.0, n) == want, (phi, n)
+            rounded_up += int(math.floor(phi * n) != want)
+    assert rounded_up > 20          # the adversarial cases are really there
+    assert oracle.fold_bin(1 / 3, 1.0, 0.0, 3) == 0
+    assert oracle.fold_bin(0.3, 1.0, 0.0, 10) == 2
+
+
 def test_fold_close_to_exact_on_generic_inputs():
     """Non-dyadic inputs: the FP64 bin equals the exact bin unless the exact
     phase lies within 1e-9 cycles of a bin edge."""
