@@ -24,9 +24,10 @@ METRIC = ("point-trials/sec (1 MI355X), split-FP32 vs FP64 at equal best-(P,Pdot
           "% VALU peak")
 
 # MI355X published peaks (AMD): FP64 vector 78.6 TFLOP/s and FP32 vector
-# 157.3 TFLOP/s (FMA = 2; the FP32 figure counts packed dual-lane ops, which
-# this library does not use).  Any VALU instruction of a wave64 issues once per
-# 4 cycles per SIMD: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-instr/s.
+# 157.3 TFLOP/s (FMA = 2).  Measured issue costs of a wave64 instruction on one
+# SIMD: 4 cycles for FP64 arithmetic, conversions, fract and integer ops, 2
+# cycles for v_fma_f32.  The VALU slot peak, one 4-cycle slot per SIMD:
+# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-slots/s.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_VALU_TLANE = 256 * 64 * 2.4e9 / 1e12
@@ -56,27 +57,59 @@ def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
     return 4.0 + 2.0 / n_pd + (n_phase * (n_mag + 1) + 2) / mean_n
 
 
-def valu_instr_per_point_trial(precision, tq):
-    """VALU instructions the kernel executes per point-trial in its fold and
-    binning (the per-segment entropy flush, ~0.3 more at 600 epochs, is not
-    counted).  FP64: fma, fract, mul, cvt and the histogram address per
-    point-trial; x and x^2 per epoch and lane, shared by the lane's tq Pdot
-    trials.  Split: fma, fract, rounding fma and the address per point-trial;
-    x, x^2, frac(x), the half-bin shift and two conversions to float per
-    epoch and lane."""
-    if precision == 0:
-        return 5.0 + 2.0 / tq
-    return 4.0 + 6.0 / tq
+def valu_instr_per_point_trial(precision, tq, w):
+    """VALU issue slots the kernel's design takes per point-trial, in units
+    of one wave64 instruction on one SIMD (4 cycles; measured on MI355X:
+    v_fma_f64, v_add_f64, v_fract_f64, v_cvt_i32_f64, v_fract_f32 and
+    v_lshl_add_u32 take 4 cycles, v_fma_f32 takes 2, i.e. half a slot).
+
+    Fold and binning, per point-trial: FP64 fma, fract, the round-down fma
+    that floors phase * n_phase, the histogram address (4 slots); split two
+    FP32 fmas (Pdot term, rounding) at half a slot, fract and the address
+    (3 slots).  Per epoch and lane, shared by the lane's tq Pdot trials:
+    FP64 x and x^2 (2); split x, x^2, frac(x), the half-bin shift and two
+    conversions (6).
+
+    Segment flush, per magnitude segment, phase bin and packed word (two
+    trials): the marginal add, two table-offset extractions and two FP64
+    adds, plus the neighbour add with overlapping bins.  A wave holds
+    ceil(tq / 2) words per bin and folds n_mag segments per work unit, so
+    over the workload this adds n_mag * n_phase * ceil(tq / 2) * k per wave
+    against sum(N) * tq point-trials per lane."""
+    import numpy as np
+    point = 4.0 + 2.0 / tq if precision == 0 else 3.0 + 6.0 / tq
+    k = 5.0 + (1.0 if w.phase_overlap else 0.0)
+    words = (tq + 1) // 2
+    lengths = np.asarray(w.lengths, dtype=np.float64)
+    flush = w.n_mag * w.n_phase * words * k * lengths.size / (tq * lengths.sum())
+    return point + flush
 
 
 def cpu_baseline(w, gpu_cube_rows, budget_s):
     """Time the oracle (as it stands) on whole curves of the same workload
     until about budget_s seconds of CPU work; compare its CE rows and minima
-    with the GPU's FP64 rows on the same curves."""
+    with the GPU's FP64 rows on the same curves.  Where one curve's full grid
+    would take more than half the budget (the paper-scale grid), every
+    sampled curve is searched over the first periods of the grid instead,
+    sized from a short probe, and there is no GPU row to compare."""
     import numpy as np
     import oracle
+    from paper_2006_06866_amd import synth
 
     threads = oracle.max_threads()
+    n_p = full_np = w.periods.size
+    probe_p = min(n_p, 2048)
+    probe = w.subset(np.arange(1))
+    t0 = time.perf_counter()
+    oracle.search(probe.times, probe.mags, probe.offsets, probe.periods[:probe_p],
+                  probe.pdots, probe.n_phase, probe.n_mag, n_threads=threads,
+                  want_cube=False, phase_overlap=w.phase_overlap)
+    per_period = (time.perf_counter() - t0) / probe_p
+    sliced = per_period * n_p > 0.5 * budget_s
+    if sliced:
+        n_p = max(probe_p, int(0.25 * budget_s / per_period))
+        w = synth.Workload(w.name, w.times, w.mags, w.offsets, w.periods[:n_p], w.pdots,
+                           w.n_phase, w.n_mag, phase_overlap=w.phase_overlap)
     done, spent, pt = 0, 0.0, 0
     max_err, best_agree, best_checked = 0.0, 0, 0
     per_curve = None
@@ -86,25 +119,27 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
         k = 1 if per_curve is None else max(1, min(w.n_curves - done,
                                                   int((budget_s - spent) / per_curve)))
         sub = w.subset(np.arange(done, done + k))
+        g = None if sliced else gpu_cube_rows(done, done + k)
         t0 = time.perf_counter()
         oc, obf, obc = oracle.search(sub.times, sub.mags, sub.offsets, sub.periods,
                                      sub.pdots, sub.n_phase, sub.n_mag, n_threads=threads,
-                                     want_cube=gpu_cube_rows(0, 0) is not None,
+                                     want_cube=g is not None,
                                      phase_overlap=w.phase_overlap)
         spent += time.perf_counter() - t0
         pt += sub.point_trials
         per_curve = spent / (done + k)
-        g = gpu_cube_rows(done, done + k)
         if g is not None and oc is not None:
             max_err = max(max_err, float(np.abs(g - oc).max()))
             best_agree += int(np.sum(g.reshape(k, -1).argmin(axis=1) == obf))
             best_checked += k
         done += k
+    grid = (f"first {n_p} of {full_np} periods x {w.pdots.size} Pdots" if sliced
+            else f"full {n_p} x {w.pdots.size} grid")
     return ({"value": pt / spent, "unit": "point-trials/s", "cores": threads,
              "kind": "oracle",
-             "sample": f"{done} of {w.n_curves} curves, full {w.periods.size} x "
-                       f"{w.pdots.size} grid, {pt:.3g} point-trials in {spent:.1f} s"},
-            {"curves_compared": done, "max_abs_dH": max_err,
+             "sample": f"{done} of {w.n_curves} curves, {grid}, {pt:.3g} point-trials "
+                       f"in {spent:.1f} s"},
+            {"curves_compared": best_checked, "max_abs_dH": max_err,
              "argmin_equal": f"{best_agree}/{best_checked}"})
 
 
@@ -190,7 +225,7 @@ def roofline(precision, w, kernel_s, config, tq):
     fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag, mean_n)
     achieved = fpp * pt / kernel_s / 1e12
     peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
-    instr = valu_instr_per_point_trial(precision, tq)
+    instr = valu_instr_per_point_trial(precision, tq, w)
     return {
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak, "traffic": measured_traffic(config, precision),
@@ -218,11 +253,20 @@ def main():
                     help="time HIP-graph replays of the whole search")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU-baseline budget; 0 skips the oracle leg")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="run the VALU issue-cost probe (paper_2006_06866_amd/valu_probe) "
+                         "and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (the "
                          "known-size kernel that scales HBM byte counters)")
     args = ap.parse_args()
 
+    if args.valu_probe:
+        import subprocess
+        probe = os.path.join(ROOT, "paper_2006_06866_amd", "valu_probe")
+        if not os.path.exists(probe):
+            raise SystemExit(f"{probe} is missing: run __graft_entry__.build() first")
+        raise SystemExit(subprocess.call([probe]))
     if args.copy_calibration > 0:
         import torch
         n = args.copy_calibration * (1 << 20) // 4

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgce.so")
+PROBE = os.path.join(PKG, "valu_probe")   # VALU issue-cost probe (bench.py --valu-probe)
 # the search-kernel variants are spread over four files so they compile in
 # parallel
 SOURCES = ["gce_kernels.hip", "gce_search_fp64.hip", "gce_search_fp64_overlap.hip",
@@ -60,7 +61,11 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
                 f.result()
         tmp = LIB + ".tmp%d" % os.getpid()
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        ptmp = PROBE + ".tmp%d" % os.getpid()
+        _run([HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+              "-packed-fp32-ops", os.path.join(CSRC, "valu_probe.hip"), "-o", ptmp], verbose)
     os.replace(tmp, LIB)
+    os.replace(ptmp, PROBE)
     return LIB
 
 

@@ -144,13 +144,16 @@ int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max
 
 int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
 {
-    // Pdot trials per lane: more trials share each point's x and x^2, but
-    // every trial pair adds a histogram region of LDS.  Measured on MI355X:
-    // 8 trials is fastest while a wave's histograms stay near 10 KiB (10
-    // phase bins: FP64 8/4/2 trials 60/64/73 ms at 512 x 600 x 20,000 x 64);
-    // at 20 KiB (20 bins) the CU holds too few waves and 4 trials wins
-    // (64 x 5,000 x 100,000 x 256: 1.25 s at 4 vs 1.70 s at 8).
-    int tq = 8;
+    // Pdot trials per lane: more trials share each epoch's x and x^2, but
+    // every trial pair adds a histogram region of LDS and registers.
+    // Measured on MI355X (kernel ms at 1 / 2 / 4 / 8 trials):
+    //   FP64, 10 x 5 bins, 512 x 600 x 20,000 x 64:     - / 59.4 / 53.1 / 54.4
+    //   FP64, 20 x 10 bins, 64 x 5,000 x 100,000 x 256: - / 1165 / 1121 / 1563
+    //   split, 10 x 5 bins, 512 x 600 x 20,000 x 64:    - / 63.6 / 50.9 / 48.3
+    //   split, 20 x 10 bins, 64 x 5,000 x ...:          - / 1213 / 1022 / 1539
+    // so FP64 starts from 4 and the split path from 8, and a wave's
+    // histograms stay within ~13 KiB (at 20 KiB the CU holds too few waves).
+    int tq = precision == GCE_PRECISION_FP64 ? 4 : 8;
     while (tq > 1 &&
            (tq >= 2 * n_pd || !gce::search_variant_exists(precision, n_phase, tq) ||
             gce::search_lds_bytes(precision, n_phase, tq, 0, max_n) > 13 * 1024))

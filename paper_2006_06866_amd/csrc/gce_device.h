@@ -20,6 +20,12 @@
 #ifndef GCE_PREFETCH
 #define GCE_PREFETCH 0          // load the next epochs during the current ones
 #endif
+#ifndef GCE_RD_GROUP
+#define GCE_RD_GROUP 8          // FP64 bin fmas per rounding-mode switch
+#endif
+#ifndef GCE_FLUSH_ACC
+#define GCE_FLUSH_ACC 4         // partial entropy sums per trial (trials_per_lane <= 2)
+#endif
 #ifndef GCE_SCALAR_EPOCHS
 #define GCE_SCALAR_EPOCHS 1     // read epoch offsets with scalar loads
 #endif
@@ -53,17 +59,143 @@ __device__ __forceinline__ uint32_t lds_add(uint32_t *p, uint32_t v)
                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// Eq. (3) phase bin in binary64, bit-identical to the documented sequence
-// y = fma(-Pdot/2, x^2, x); phi = y - floor(y); bin = (int)(phi * n_phase).
-// v_fract_f64 returns y - floor(y) clamped to 1 - 2^-53; the clamp maps a
-// phase that rounds up to 1 into the last bin, as the reference clamp does,
-// and (1 - 2^-53) * n < n for every bin count n, so no clamp is needed.
-__device__ __forceinline__ int fp64_phase_bin(double x, double x2,
-                                              double half_pdot, double nph)
+// Eq. (3) phase bins in binary64, bit-identical to the documented sequence
+// y = fma(-Pdot/2, x^2, x); phi = y - floor(y); bin = floor(phi * n_phase),
+// the floor taken of the exact product.
+//  - v_fract_f64 returns y - floor(y) clamped to 1 - 2^-53: a phase that
+//    rounds up to 1 lands in the last bin, as floor((1 - 2^-53) n) = n - 1.
+//  - floor(phi * n) exactly: one fma phi * n + 2^52 rounded toward minus
+//    infinity.  Doubles in [2^52, 2^53) are the integers, so the result is
+//    2^52 + floor(phi * n) and its low word is the bin (phi * n < 128).  The
+//    MODE register's FP64 rounding field (bits 3:2; 2 = toward -inf, 0 =
+//    nearest even) is switched around these fmas only, inside one asm block
+//    so that no other floating-point instruction runs in that mode.
+constexpr uint64_t kTwo52Bits = 0x4330000000000000ull;
+
+template <int T>
+__device__ __forceinline__ void fp64_floor_products(double (&phi)[T], double n,
+                                                    uint32_t (&bin)[T]);
+
+// The FP_ROUND field is written twice per block; two writes of one hardware
+// register need two wait states between them, which the fmas (or, for a
+// single fma, an s_nop) provide.  Vector instructions need none after it.
+#define GCE_RD_BEGIN "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\t"
+#define GCE_RD_END "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0"
+
+template <>
+__device__ __forceinline__ void fp64_floor_products<1>(double (&phi)[1], double n,
+                                                       uint32_t (&bin)[1])
 {
-    const double y = __builtin_fma(-half_pdot, x2, x);
-    const double fr = __builtin_amdgcn_fract(y);
-    return (int)(fr * nph);
+    const double m = __longlong_as_double((long long)kTwo52Bits);
+    asm volatile(GCE_RD_BEGIN
+                 "v_fma_f64 %0, %0, %1, %2\n\t"
+                 "s_nop 1\n\t"
+                 GCE_RD_END
+                 : "+v"(phi[0])
+                 : "s"(n), "v"(m));
+#pragma unroll
+    for (int t = 0; t < 1; ++t) bin[t] = (uint32_t)__double2loint(phi[t]);
+}
+
+template <>
+__device__ __forceinline__ void fp64_floor_products<2>(double (&phi)[2], double n,
+                                                       uint32_t (&bin)[2])
+{
+    const double m = __longlong_as_double((long long)kTwo52Bits);
+    asm volatile(GCE_RD_BEGIN
+                 "v_fma_f64 %0, %0, %2, %3\n\t"
+                 "v_fma_f64 %1, %1, %2, %3\n\t"
+                 GCE_RD_END
+                 : "+v"(phi[0]), "+v"(phi[1])
+                 : "s"(n), "v"(m));
+#pragma unroll
+    for (int t = 0; t < 2; ++t) bin[t] = (uint32_t)__double2loint(phi[t]);
+}
+
+template <>
+__device__ __forceinline__ void fp64_floor_products<4>(double (&phi)[4], double n,
+                                                       uint32_t (&bin)[4])
+{
+    const double m = __longlong_as_double((long long)kTwo52Bits);
+    asm volatile(GCE_RD_BEGIN
+                 "v_fma_f64 %0, %0, %4, %5\n\t"
+                 "v_fma_f64 %1, %1, %4, %5\n\t"
+                 "v_fma_f64 %2, %2, %4, %5\n\t"
+                 "v_fma_f64 %3, %3, %4, %5\n\t"
+                 GCE_RD_END
+                 : "+v"(phi[0]), "+v"(phi[1]), "+v"(phi[2]), "+v"(phi[3])
+                 : "s"(n), "v"(m));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bin[t] = (uint32_t)__double2loint(phi[t]);
+}
+
+template <>
+__device__ __forceinline__ void fp64_floor_products<8>(double (&phi)[8], double n,
+                                                       uint32_t (&bin)[8])
+{
+    const double m = __longlong_as_double((long long)kTwo52Bits);
+    asm volatile(GCE_RD_BEGIN
+                 "v_fma_f64 %0, %0, %8, %9\n\t"
+                 "v_fma_f64 %1, %1, %8, %9\n\t"
+                 "v_fma_f64 %2, %2, %8, %9\n\t"
+                 "v_fma_f64 %3, %3, %8, %9\n\t"
+                 "v_fma_f64 %4, %4, %8, %9\n\t"
+                 "v_fma_f64 %5, %5, %8, %9\n\t"
+                 "v_fma_f64 %6, %6, %8, %9\n\t"
+                 "v_fma_f64 %7, %7, %8, %9\n\t"
+                 GCE_RD_END
+                 : "+v"(phi[0]), "+v"(phi[1]), "+v"(phi[2]), "+v"(phi[3]), "+v"(phi[4]), "+v"(phi[5]), "+v"(phi[6]), "+v"(phi[7])
+                 : "s"(n), "v"(m));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) bin[t] = (uint32_t)__double2loint(phi[t]);
+}
+
+template <>
+__device__ __forceinline__ void fp64_floor_products<16>(double (&phi)[16], double n,
+                                                       uint32_t (&bin)[16])
+{
+    const double m = __longlong_as_double((long long)kTwo52Bits);
+    asm volatile(GCE_RD_BEGIN
+                 "v_fma_f64 %0, %0, %16, %17\n\t"
+                 "v_fma_f64 %1, %1, %16, %17\n\t"
+                 "v_fma_f64 %2, %2, %16, %17\n\t"
+                 "v_fma_f64 %3, %3, %16, %17\n\t"
+                 "v_fma_f64 %4, %4, %16, %17\n\t"
+                 "v_fma_f64 %5, %5, %16, %17\n\t"
+                 "v_fma_f64 %6, %6, %16, %17\n\t"
+                 "v_fma_f64 %7, %7, %16, %17\n\t"
+                 "v_fma_f64 %8, %8, %16, %17\n\t"
+                 "v_fma_f64 %9, %9, %16, %17\n\t"
+                 "v_fma_f64 %10, %10, %16, %17\n\t"
+                 "v_fma_f64 %11, %11, %16, %17\n\t"
+                 "v_fma_f64 %12, %12, %16, %17\n\t"
+                 "v_fma_f64 %13, %13, %16, %17\n\t"
+                 "v_fma_f64 %14, %14, %16, %17\n\t"
+                 "v_fma_f64 %15, %15, %16, %17\n\t"
+                 GCE_RD_END
+                 : "+v"(phi[0]), "+v"(phi[1]), "+v"(phi[2]), "+v"(phi[3]), "+v"(phi[4]), "+v"(phi[5]), "+v"(phi[6]), "+v"(phi[7]), "+v"(phi[8]), "+v"(phi[9]), "+v"(phi[10]), "+v"(phi[11]), "+v"(phi[12]), "+v"(phi[13]), "+v"(phi[14]), "+v"(phi[15])
+                 : "s"(n), "v"(m));
+#pragma unroll
+    for (int t = 0; t < 16; ++t) bin[t] = (uint32_t)__double2loint(phi[t]);
+}
+
+#undef GCE_RD_BEGIN
+#undef GCE_RD_END
+
+// Bins of G epochs under T Pdot trials each (x = dt / P, x2 = x^2 per
+// epoch): bin[g * T + t].  All G * T round-down fmas share one mode switch.
+template <int G, int T>
+__device__ __forceinline__ void fp64_phase_bins(const double (&x)[G], const double (&x2)[G],
+                                                const double (&half_pdot)[T], double nph,
+                                                uint32_t (&bin)[G * T])
+{
+    double phi[G * T];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            phi[g * T + t] = __builtin_amdgcn_fract(__builtin_fma(-half_pdot[t], x2[g], x[g]));
+    fp64_floor_products<G * T>(phi, nph, bin);
 }
 
 __device__ __forceinline__ bool lex_less(double h1, int64_t f1, double h2,

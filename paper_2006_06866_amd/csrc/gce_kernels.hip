@@ -351,7 +351,10 @@ __global__ __launch_bounds__(64) void k_debug_counts(
             if (dp.precision == kPrecFp64) {
                 const double x = dt * invp;
                 const double x2 = x * x;
-                b = fp64_phase_bin(x, x2, ha, (double)nph);
+                const double hpd[1] = {ha}, xs[1] = {x}, x2s[1] = {x2};
+                uint32_t bb[1];
+                fp64_phase_bins<1, 1>(xs, x2s, hpd, (double)nph, bb);
+                b = (int)bb[0];
             } else {
                 const SplitPoint sp = split_point(dt, invp, half_bin);
                 b = (int)(split_slot_bits(sp, ha32, (float)nph) - kRoundMagicBits);

@@ -431,3 +431,39 @@ def test_automatic_table_placement():
     assert info([500] * 4, 50, 10, True)["table_in_lds"] == 1   # paper scale
     assert info([3000] * 4, 50, 10)["table_in_lds"] == 0        # table over 8 KiB
     assert info([100] * 4, 128, 5, n_pd=1)["table_in_lds"] == 0  # LDS budget
+
+
+@pytest.mark.parametrize("n_phase", [3, 10, 50, 128])
+def test_fp64_bins_on_bin_edges_are_exact_floor(n_phase):
+    """Phases on every bin edge k/n and one ulp either side (dt = phase with
+    t0 = 0, P = 1, Pdot = 0, so the fold returns the phase unchanged): the
+    FP64 path bins each at floor(phi * n) of the exact product, like the
+    oracle; the rounded product would move many of them up a bin."""
+    import math
+    from fractions import Fraction
+    phis = {0.0}
+    for k in range(n_phase + 1):
+        e = k / n_phase
+        for v in (e, math.nextafter(e, 0.0), math.nextafter(e, 1.0)):
+            if 0.0 <= v < 1.0:
+                phis.add(v)
+    t = np.array(sorted(phis))
+    m = np.zeros_like(t)
+    want = np.bincount([min(math.floor(Fraction(v) * n_phase), n_phase - 1) for v in t],
+                       minlength=n_phase)
+    if n_phase & (n_phase - 1):   # k/n inexact: some rounded products land on k
+        assert not np.array_equal(want, np.bincount(
+            np.minimum((t * n_phase).astype(int), n_phase - 1), minlength=n_phase))
+    off = np.array([0, t.size], dtype=np.int64)
+    w = synth.Workload("edges", t, m, off, np.array([1.0]), np.array([0.0]), n_phase, 1)
+    plan = gce.Plan(off, 1, 1, n_phase, 1)
+    got = plan.debug_counts(*upload(w), np.array([0]), np.array([0]))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().astype(np.int64).reshape(-1), want)
+    assert np.array_equal(oracle.counts(t, m, 1.0, 0.0, n_phase, 1).reshape(-1), want)
+    plan.close()
+    # the search kernel over a few dyadic periods, against the oracle
+    m2 = np.random.default_rng(n_phase).normal(size=t.size)
+    w2 = synth.Workload("edges2", t, m2, off, np.array([1.0, 0.5, 0.25, 2.0, 4.0]),
+                        np.array([0.0, 2.0 ** -30]), n_phase, 3)
+    _full_parity(w2, f"edges n={n_phase}", counts_sample=20)
