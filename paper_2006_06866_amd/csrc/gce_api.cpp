@@ -139,7 +139,8 @@ int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max
                       int64_t median_n)
 {
     return max_n <= 1023 && 4 * (int64_t)n_phase * n_mag >= median_n &&
-           gce::search_lds_bytes(precision, n_phase, tq, 1, max_n) <= 20 * 1024;
+           gce::search_lds_bytes(precision, n_phase, tq, 1, max_n) <=
+               (size_t)gce::search_waves_per_block(1) * 20 * 1024;
 }
 
 int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
@@ -522,8 +523,10 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
     if (!pl || !info) return fail(GCE_EINVAL, "NULL argument");
     info->precision = pl->dp.precision;
     info->trials_per_lane = pl->dp.tq;
-    info->lds_bytes_per_wave = (int32_t)gce::search_lds_bytes(
-        pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds, pl->dp.max_n);
+    info->lds_bytes_per_wave = (int32_t)(
+        gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds,
+                              pl->dp.max_n) /
+        gce::search_waves_per_block(pl->dp.lut_lds));
     info->table_in_lds = pl->dp.lut_lds;
     info->work_units = pl->dp.n_units;
     info->workspace_bytes = (int64_t)pl->ws_bytes;

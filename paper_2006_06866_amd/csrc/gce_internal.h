@@ -107,8 +107,12 @@ SearchTable search_table_split_overlap();
 
 // Search-kernel variants compiled into the library.
 bool search_variant_exists(int precision, int n_phase, int tq);
-// Bytes of LDS one search wave uses (lut_lds: the c ln c table of max_n + 1
-// entries is kept in LDS too).
+// Waves per search block: the waves of a block share the LDS copy of the
+// c ln c table.
+constexpr int kLutWaves = 2;
+inline int search_waves_per_block(int lut_lds) { return lut_lds ? kLutWaves : 1; }
+// Bytes of LDS one search block uses (lut_lds: the c ln c table of max_n + 1
+// entries is kept in LDS too, once per block).
 size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_n);
 
 }  // namespace gce

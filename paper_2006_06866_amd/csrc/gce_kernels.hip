@@ -226,8 +226,8 @@ size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max
     const size_t slots = (size_t)n_phase + (precision == kPrecSplit ? 1 : 0);
     const size_t hist = regions * slots * kWave * sizeof(uint32_t);
     const size_t marg = regions * (size_t)n_phase * kWave * sizeof(uint32_t);
-    size_t bytes = (v && v->nph == 0) ? hist + marg : hist;
-    if (lut_lds) bytes = ((bytes + 7) & ~(size_t)7) + sizeof(double) * (size_t)(max_n + 1);
+    size_t bytes = ((v && v->nph == 0) ? hist + marg : hist) * search_waves_per_block(lut_lds);
+    if (lut_lds) bytes += sizeof(double) * (size_t)(max_n + 1);
     return bytes;
 }
 
@@ -237,9 +237,11 @@ hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
         find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds);
     if (!v) return hipErrorInvalidValue;
     const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_n);
-    const int64_t gx = dp.n_units < kSearchGridX ? dp.n_units : kSearchGridX;
-    const int64_t gy = (dp.n_units + gx - 1) / gx;
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave), lds, s,
+    const int wpb = search_waves_per_block(dp.lut_lds);
+    const int64_t blocks = (dp.n_units + wpb - 1) / wpb;
+    const int64_t gx = blocks < kSearchGridX ? blocks : kSearchGridX;
+    const int64_t gy = (blocks + gx - 1) / gx;
+    hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave * wpb), lds, s,
                        dp, out_ce);
     return hipGetLastError();
 }

@@ -37,25 +37,39 @@ struct SearchShape {
     static constexpr int kFlushGroup = kRegions >= 8 ? 1 : 8 / kRegions;
 };
 
-// LL = 1: the c ln c table is copied into LDS behind the histograms (for
-// shapes with many cells per epoch, where the segment flush dominates).
+// LL = 1: the c ln c table is copied into LDS, shared by the block's
+// search_waves_per_block(1) waves (for shapes with many cells per epoch,
+// where the segment flush dominates).
 // OVL = 1: 50%-overlapping phase bins (each epoch counts in two bins).
 template <int PREC, int NPH, int TQ, int LL, int OVL>
-__global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
-                                                                  void *out_ce_v)
+__global__ __launch_bounds__(kWave * (LL ? kLutWaves : 1)) GCE_SEARCH_ATTR
+void k_search(DevPlan dp, void *out_ce_v)
 {
     using S = SearchShape<PREC, NPH, TQ>;
     using OutT = typename std::conditional<PREC == kPrecFp64, double, float>::type;
     constexpr int R = S::kRegions;
+    constexpr int WPB = LL ? kLutWaves : 1;             // waves per block
     extern __shared__ uint32_t lds[];
     OutT *__restrict__ out_ce = static_cast<OutT *>(out_ce_v);
 
-    const int lane = threadIdx.x;
+    const int lane = WPB > 1 ? (int)(threadIdx.x % kWave) : (int)threadIdx.x;
+    // the wave's index in the block is uniform across its lanes: say so, so
+    // that everything derived from the work unit stays in scalar registers
+    const int wave = WPB > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) : 0;
     const int nph = NPH > 0 ? NPH : dp.n_phase;
     const int nslot = nph + S::kWrap;                   // LDS words per region
+    // LDS: [c ln c table (LL)] then one region per wave:
+    // [R][nslot][64] histogram words, then [R][nph][64] marginals (NPH == 0)
+    const size_t table_words = LL ? (size_t)2 * (dp.max_n + 1) : 0;
+    const size_t wave_words = (size_t)R * (nslot + (S::kLdsMarg ? nph : 0)) * kWave;
+    double *lut_lds = reinterpret_cast<double *>(lds);
+    if (LL) {   // before any wave of the block may leave
+        for (int c = threadIdx.x; c <= dp.max_n; c += kWave * WPB) lut_lds[c] = dp.lut[c];
+        __syncthreads();
+    }
     // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
-    // unit = y * gridDim.x + x, in dispatch order
-    const int64_t u = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    // unit = (y * gridDim.x + x) * WPB + wave, in dispatch order
+    const int64_t u = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * WPB + wave;
     if (u >= dp.n_units) return;
     const int64_t rank = u / dp.units_per_curve;
     const int64_t rem = u - rank * dp.units_per_curve;
@@ -92,15 +106,8 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
         else ha32[t] = dp.half_pd32[q];
     }
 
-    uint32_t *hist = lds;                                  // [R][nslot][64]
-    uint32_t *lmarg = lds + (size_t)R * nslot * kWave;     // [R][nph][64] (NPH == 0)
-    // LDS copy of the c ln c table, 8-byte aligned, after the count words
-    double *lut_lds = reinterpret_cast<double *>(
-        lds + (((size_t)R * (nslot + (S::kLdsMarg ? nph : 0)) * kWave + 1) & ~(size_t)1));
-    if (LL) {
-        for (int c = lane; c <= dp.max_n; c += kWave) lut_lds[c] = dp.lut[c];
-        __syncthreads();
-    }
+    uint32_t *hist = lds + table_words + wave * wave_words;  // [R][nslot][64]
+    uint32_t *lmarg = hist + (size_t)R * nslot * kWave;      // [R][nph][64] (NPH == 0)
     for (int i = 0; i < R * nslot; ++i) hist[i * kWave + lane] = 0;
     if (S::kLdsMarg)
         for (int i = 0; i < R * nph; ++i) lmarg[i * kWave + lane] = 0;
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kWave) GCE_SEARCH_ATTR void k_search(DevPlan dp,
     uniform_i32 *segc = (uniform_i32 *)(dp.seg + (int64_t)c * (dp.n_mag + 1));
     const double *__restrict__ lut = LL ? lut_lds : dp.lut;
     uint32_t *hcol = hist + lane;
-    char *lbytes = reinterpret_cast<char *>(lds);
+    char *lbytes = reinterpret_cast<char *>(hist);     // this wave's histogram words
 
     // With the table in LDS (LL), counts are kept in units of 8 (at most
     // 8 * 8191 per 16-bit half), so a half is directly the byte offset of
