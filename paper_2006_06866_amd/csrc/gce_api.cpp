@@ -424,10 +424,11 @@ int gce_plan_execute(gce_plan_t pl, const double *times, const double *mags,
     if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const DevPlan &dp = pl->dp;
-    hipError_t e = gce::launch_grid_setup(dp, periods, pdots, s);
-    if (e != hipSuccess) return fail_hip(e, "grid set-up launch");
-    e = gce::launch_prepass(dp, times, mags, s);
+    // the prepass sets the grid-validity flag that the grid set-up may clear
+    hipError_t e = gce::launch_prepass(dp, times, mags, s);
     if (e != hipSuccess) return fail_hip(e, "prepass launch");
+    e = gce::launch_grid_setup(dp, periods, pdots, s);
+    if (e != hipSuccess) return fail_hip(e, "grid set-up launch");
     const bool timed = !pl->ev_start.empty();
     const size_t slot = timed ? (size_t)(pl->n_timed % (int64_t)pl->ev_start.size()) : 0;
     if (timed && (e = hipEventRecord(pl->ev_start[slot], s)) != hipSuccess)
@@ -460,8 +461,8 @@ int gce_plan_debug_counts(gce_plan_t pl, const double *times,
     if (!guard.ok) return fail(GCE_ENODEV, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const DevPlan &dp = pl->dp;
-    hipError_t e = gce::launch_grid_setup(dp, periods, pdots, s);
-    if (e == hipSuccess) e = gce::launch_prepass(dp, times, mags, s);
+    hipError_t e = gce::launch_prepass(dp, times, mags, s);
+    if (e == hipSuccess) e = gce::launch_grid_setup(dp, periods, pdots, s);
     if (e == hipSuccess)
         e = gce::launch_debug_counts(dp, trial_curve, trial_flat, n_trials, out_counts, s);
     if (e != hipSuccess) return fail_hip(e, "debug counts launch");

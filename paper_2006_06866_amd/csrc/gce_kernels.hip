@@ -2,9 +2,9 @@
 // (P, Pdot) search of Katz et al. 2020, Sec. 2.3.
 //
 // Pipeline of one execution (all on the caller's stream):
-//   k_grid_setup  1/P and Pdot/2 per grid value, grid validity      (trial setup)
 //   k_prepass     per curve: t0, magnitude bins, points grouped by
 //                 magnitude bin (stable counting sort)               (prepass)
+//   k_grid_setup  1/P and Pdot/2 per grid value, grid validity      (trial setup)
 //   k_search      the fold of Eq. (3), 2-D histogram, Eq. (4)        (hot loop,
 //                 gce_search.h, instantiated by gce_search_*.hip)
 //   k_epilogue    per-curve minimum over the work units              (argmin)
@@ -34,39 +34,44 @@ hipError_t launch_lut(const DevPlan &dp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// trial setup: 1/P (correctly rounded division), Pdot/2 (exact), validity
+// trial setup: 1/P (correctly rounded division), Pdot/2 (exact), validity.
+// Grid-stride over the period and Pdot axes.  The prepass (launched first)
+// sets grid_ok to 1; any thread that meets an invalid value stores 0 (all
+// writers store the same value, so no atomics are needed).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_grid_setup(DevPlan dp,
-                                                    const double *periods,
-                                                    const double *pdots)
+constexpr int kGridBlock = 256;
+
+__global__ __launch_bounds__(kGridBlock) void k_grid_setup(DevPlan dp,
+                                                          const double *periods,
+                                                          const double *pdots)
 {
-    __shared__ int bad_sh;
-    if (threadIdx.x == 0) bad_sh = 0;
-    __syncthreads();
-    int bad = 0;
-    for (int64_t p = threadIdx.x; p < dp.n_p; p += blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (int64_t p = i0; p < dp.n_p; p += stride) {
         const double P = periods[p];
         const bool ok = P >= kMinPeriod && P <= kMaxPeriod;  // false for NaN
         bad |= !ok;
         dp.inv_p[p] = ok ? 1.0 / P : 1.0;
     }
-    for (int64_t q = threadIdx.x; q < dp.n_pd; q += blockDim.x) {
+    for (int64_t q = i0; q < dp.n_pd; q += stride) {
         const double Pd = pdots[q];
         const bool ok = fabs(Pd) <= kMaxAbsPdot;             // false for NaN
         bad |= !ok;
         dp.half_pd[q] = ok ? 0.5 * Pd : 0.0;
         dp.half_pd32[q] = ok ? (float)(0.5 * Pd) : 0.0f;
     }
-    if (bad) atomicOr(&bad_sh, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) *dp.grid_ok = bad_sh ? 0 : 1;
+    if (bad) *dp.grid_ok = 0;
 }
 
 hipError_t launch_grid_setup(const DevPlan &dp, const double *periods,
                              const double *pdots, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(256), 0, s, dp, periods,
-                       pdots);
+    const int64_t n = dp.n_p > dp.n_pd ? dp.n_p : dp.n_pd;
+    int64_t blocks = (n + kGridBlock - 1) / kGridBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_grid_setup, dim3((unsigned)blocks), dim3(kGridBlock), 0, s, dp,
+                       periods, pdots);
     return hipGetLastError();
 }
 
@@ -103,6 +108,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     __shared__ int bad_sh;
 
     const int64_t c = blockIdx.x;
+    if (c == 0 && threadIdx.x == 0) *dp.grid_ok = 1;   // the grid set-up may clear it
     const int64_t base = dp.off[c];
     const int32_t n = (int32_t)(dp.off[c + 1] - base);
     const int32_t n_mag = dp.n_mag;
