@@ -3,7 +3,8 @@
 // Sec. 2.3).  Instantiated by the gce_search_*.hip files, one per precision
 // and phase-bin kind, so the variants compile in parallel.
 //
-// Search-kernel layout (one wave = one work unit):
+// Search-kernel layout (one wave = one work unit; a block holds one wave, or
+// two sharing an LDS copy of the c ln c table):
 //   lane l          <-> period index p = 64 * tile + l
 //   trial t < TQ    <-> Pdot index q = TQ * group + t (same for the wave)
 //   epoch k         <-> uniform across the wave: dt_k is read with scalar
@@ -11,11 +12,12 @@
 // Epochs are pre-grouped by magnitude bin, so each lane only keeps a 1-D
 // phase histogram per trial (the paper's Sec. 2.3 GPU observation that one
 // magnitude value's phase counts suffice); at the end of each magnitude
-// segment the histogram is folded into the entropy sums and cleared.
-// Histograms live in LDS as [trial pair][phase bin][lane] 32-bit words: the
-// low and high 16 bits count trials 2r and 2r+1, so one ds_add_u32 bins one
-// point-trial, and lanes always hit distinct banks.  The marginal phase
-// counts accumulate in registers.
+// segment the histogram is folded into the entropy sums (and cleared, or,
+// with the table in LDS, left to accumulate).  Histograms live in LDS as
+// [trial pair][phase bin][lane] 32-bit words: the low and high 16 bits count
+// trials 2r and 2r+1, so one ds_add_u32 bins one point-trial, and lanes
+// always hit distinct banks.  The marginal phase counts accumulate in
+// registers.  The FP64 bin is one round-down fma (fp64_phase_bins).
 //
 // Entropy: N * H = sum_b c_b ln c_b - sum_{j,b} c_jb ln c_jb, which equals
 // Eq. (4) multiplied by N; c ln c comes from a table built on the device.
