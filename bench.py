@@ -191,14 +191,22 @@ def _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph):
 SEARCH_SOURCES = ("gce_search.h", "gce_device.h")
 
 
-def search_source_sha256():
-    """sha256 over the search kernel's sources (the template and its device
-    helpers), which the committed counter summaries are tied to."""
+def search_source_sha256(texts=None):
+    """sha256 over the search kernel's code (the template and its device
+    helpers, with // comments and blank lines dropped), which the committed
+    counter summaries are tied to."""
     import hashlib
     h = hashlib.sha256()
-    for name in SEARCH_SOURCES:
-        with open(os.path.join(ROOT, "paper_2006_06866_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    if texts is None:
+        texts = []
+        for name in SEARCH_SOURCES:
+            with open(os.path.join(ROOT, "paper_2006_06866_amd", "csrc", name)) as f:
+                texts.append(f.read())
+    for text in texts:
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 
