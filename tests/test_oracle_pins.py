@@ -112,6 +112,30 @@ def test_phase_bin_is_floor_of_exact_product():
     assert oracle.fold_bin(0.3, 1.0, 0.0, 10) == 2
 
 
+def test_phase_rounding_up_to_one_lands_in_last_bin():
+    """A fold result y just below 0 (|y| < 2^-54): y - floor(y) rounds to 1,
+    while its exact value 1 - |y| lies in the last bin.  Inputs from an exact
+    search: dt = x = 1 + k 2^-30, P = 1, Pdot = 2a with a = fl(x / fl(x^2))
+    or a neighbour, so that fma(-a, fl(x^2), x) is a tiny negative number."""
+    cases = []
+    for k in range(1, 20000):
+        x = 1.0 + k * 2.0 ** -30
+        x2 = x * x
+        a0 = x / x2
+        for a in (a0, math.nextafter(a0, 0.0), math.nextafter(a0, 2.0)):
+            y = float(Fraction(x) - Fraction(a) * Fraction(x2))   # the fma, rounded once
+            if -2.0 ** -54 < y < 0.0:
+                cases.append((x, 2.0 * a, Fraction(x) - Fraction(a) * Fraction(x2)))
+        if len(cases) >= 3:
+            break
+    assert len(cases) >= 3
+    for x, pdot, y_exact in cases:
+        phi_exact = y_exact - math.floor(y_exact)
+        for n in (3, 10, 50):
+            assert math.floor(phi_exact * n) == n - 1
+            assert oracle.fold_bin(x, 1.0, pdot, n) == n - 1
+
+
 def test_fold_close_to_exact_on_generic_inputs():
     """Non-dyadic inputs: the FP64 bin equals the exact bin unless the exact
     phase lies within 1e-9 cycles of a bin edge."""
