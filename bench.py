@@ -244,6 +244,55 @@ def roofline(precision, w, kernel_s, config, tq):
     }
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timing_sweep():
+    """Sec. 2.3.2 timing figure axes on synthetic noise curves: for each
+    (n_phase, N, search points, n_Pdot) the FP64 search kernel's time per
+    light curve per search point, from HIP events over 3 executes of a plan
+    holding enough curves for a measurable launch."""
+    import numpy as np
+    import torch
+    import paper_2006_06866_amd as gce
+    from paper_2006_06866_amd import synth
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for n_phase in (15, 50):
+        for n in (100, 1000):
+            for n_search in (10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7):
+                for n_pd in (1, 32):
+                    n_p = max(1, n_search // n_pd)
+                    k = int(max(1, min(512, 2e10 // (n * n_p * n_pd))))
+                    w = synth.random_curves(7 + n_phase + n, [n] * k, n_freq=n_p,
+                                            n_pdots=n_pd, n_phase=n_phase, n_mag=10,
+                                            pdot_scale=1e-12)
+                    inputs = [torch.from_numpy(a).to(dev)
+                              for a in (w.times, w.mags, w.periods, w.pdots)]
+                    plan = gce.Plan(w.offsets, n_p, n_pd, n_phase, 10, device=dev)
+                    best = plan.new_best()
+                    plan.execute(*inputs, out_best=best)
+                    plan.set_timing(3)
+                    for _ in range(3):
+                        plan.execute(*inputs, out_best=best)
+                    torch.cuda.synchronize()
+                    ms = float(np.median(plan.search_times_ms()))
+                    info = plan.info()
+                    plan.close()
+                    rows.append({"n_phase": n_phase, "N": n, "search_points": n_p * n_pd,
+                                 "n_pdot": n_pd, "curves": k,
+                                 "trials_per_lane": info["trials_per_lane"],
+                                 "table_in_lds": info["table_in_lds"], "kernel_ms": ms,
+                                 "ns_per_curve_per_point": ms * 1e6 / (k * n_p * n_pd),
+                                 "point_trials_per_s": k * n * n_p * n_pd / (ms * 1e-3)})
+                    log(f"sweep {rows[-1]}")
+    print(json.dumps({"sweep": rows, "kernel": "k_search<fp64>",
+                      "data": "synthetic noise curves, uniform epochs"}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +310,10 @@ def main():
                     help="time HIP-graph replays of the whole search")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU-baseline budget; 0 skips the oracle leg")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time per light curve per search point over n_phase in {15, 50}, "
+                         "N in {100, 1000}, 1e3..1e7 search points at n_Pdot 1 and 32 "
+                         "(the axes of the paper's timing figure), one JSON line")
     ap.add_argument("--valu-probe", action="store_true",
                     help="run the VALU issue-cost probe (paper_2006_06866_amd/valu_probe) "
                          "and exit")
@@ -269,6 +322,8 @@ def main():
                          "known-size kernel that scales HBM byte counters)")
     args = ap.parse_args()
 
+    if args.sweep:
+        raise SystemExit(timing_sweep())
     if args.valu_probe:
         import subprocess
         probe = os.path.join(ROOT, "paper_2006_06866_amd", "valu_probe")
@@ -302,7 +357,6 @@ def main():
     w = synth.make_config(args.config)
     if 0 < args.curves < w.n_curves:
         w = w.subset(range(args.curves))
-    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     log(f"workload {WORKLOADS[args.config]}: {w.point_trials:.3g} point-trials")
     inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
     pt = w.point_trials

@@ -467,3 +467,34 @@ def test_fp64_bins_on_bin_edges_are_exact_floor(n_phase):
     w2 = synth.Workload("edges2", t, m2, off, np.array([1.0, 0.5, 0.25, 2.0, 4.0]),
                         np.array([0.0, 2.0 ** -30]), n_phase, 3)
     _full_parity(w2, f"edges n={n_phase}", counts_sample=20)
+
+
+def test_tilings_agree():
+    """Every tiling the plan or the autotuner may choose (1, 2, 4, 8 trials
+    per lane x c ln c table in global memory or LDS) gives the same
+    histograms (one bin code), CE values equal to rounding (sum orders
+    differ between tilings), and the same minimum or one tied within it."""
+    w = synth.random_curves(321, [64, 200, 600, 1000], n_freq=300, n_pdots=9,
+                            n_phase=10, n_mag=5, pdot_scale=5e-9)
+    ref = None
+    rng = np.random.default_rng(3)
+    ci = rng.integers(0, w.n_curves, 300)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, 300)
+    for tq in (1, 2, 4, 8):
+        for placement in (gce.TABLE_GLOBAL, gce.TABLE_LDS):
+            plan, dev, cube, best = run_gpu(w, trials_per_lane=tq, table_placement=placement)
+            got = (cube.cpu().numpy(), gce.best_fields(best),
+                   plan.debug_counts(*dev, ci, fi).cpu().numpy())
+            plan.close()
+            if ref is None:
+                ref = got
+                continue
+            n = w.lengths[:, None, None].astype(np.float64)
+            tol = ce_tolerance(ref[0], w.n_phase, w.n_mag, n)
+            assert np.all(np.abs(got[0] - ref[0]) <= tol), (tq, placement)
+            assert np.array_equal(got[2], ref[2]), (tq, placement)
+            for c in range(w.n_curves):
+                f0, f1 = int(ref[1]["flat_index"][c]), int(got[1]["flat_index"][c])
+                if f0 != f1:
+                    q, p = divmod(f1, w.periods.size)
+                    assert ref[0][c, q, p] <= ref[1]["ce_min"][c] + 2 * tol[c, 0, 0], (tq, placement, c)

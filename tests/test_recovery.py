@@ -46,3 +46,17 @@ def test_paper_grid_size():
     p = synth.paper_grid()
     assert p.size == 5183995
     assert abs(1 / p[-1] - 480.0) < 1e-6 and abs(1 / p[0] - 2 / 3600) < 1e-15
+
+
+def test_pdot_resolution_period_matches_paper():
+    """Eqs. (6)-(7): the period below which a 10-yr search with n_b phase bins
+    resolves the GW Pdot solves P = (n_b |Pdot(P)| / 2)^(1/2) t; for the
+    0.61 / 0.21 Msun binary it is 33.2 min at n_b = 50 (the paper: P* of
+    order 30-40 min) and 21.4 min at n_b = 10."""
+    mc = synth.chirp_mass(0.61, 0.21)
+    t = 10 * synth.YEAR
+    for nb, want in ((50, 33.2), (10, 21.4)):
+        p = 30 * synth.MINUTE
+        for _ in range(200):       # a contraction: the map's slope is -5/6
+            p = math.sqrt(0.5 * nb * abs(synth.pdot_gw(p, mc))) * t
+        assert abs(p / synth.MINUTE - want) < 0.05
