@@ -240,7 +240,7 @@ int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
         if (n > gce::kMaxPoints) return fail(GCE_EINVAL, "curve longer than 65535 epochs");
         max_n = std::max(max_n, n);
     }
-    // kernel grids are 1-D with at most 2^31 - 1 work units
+    // index arithmetic in the kernels keeps tiles and Pdot groups in 32 bits
     const int64_t n_ptiles = (n_p + gce::kWave - 1) / gce::kWave;
     if (n_ptiles > (int64_t)1 << 30 || n_pd > (int64_t)1 << 30)
         return fail(GCE_EINVAL, "grid too large");

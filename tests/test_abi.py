@@ -77,6 +77,9 @@ def test_bad_options_rejected_on_host():
     with pytest.raises(gce.GceError) as ei:
         gce.Plan(np.array([0, 5]), 10, 2, 10, 5, precision=7, device="cuda:0")
     assert ei.value.status == -1
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(np.array([0, 5]), 10, 2, 10, 5, table_placement=3, device="cuda:0")
+    assert ei.value.status == -1
 
 
 def test_null_plan_and_pointers_rejected():
