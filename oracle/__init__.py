@@ -49,6 +49,8 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_LIB)
         lib.ce_oracle_mag_bins.argtypes = [_d, ctypes.c_int64, ctypes.c_int32, _i32]
+        lib.ce_oracle_mag_bins2.argtypes = [_d, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_int32, _i32, _i32]
         lib.ce_oracle_fold_bin.argtypes = [ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int32]
         lib.ce_oracle_fold_bin.restype = ctypes.c_int32
@@ -104,6 +106,24 @@ def mag_bins(mags, n_mag: int) -> np.ndarray:
     return out
 
 
+def mag_bins_overlap(mags, n_mag: int):
+    """50%-overlapping magnitude bins of one curve: (first, second) bin of
+    every epoch, second = -1 where the epoch is in one bin only."""
+    m = _f64(mags)
+    a = np.empty(m.size, dtype=np.int32)
+    b = np.empty(m.size, dtype=np.int32)
+    rc = _load().ce_oracle_mag_bins2(_p(m, _d), m.size, n_mag, 1, _p(a, _i32),
+                                     _p(b, _i32))
+    _check(rc, "mag_bins_overlap")
+    if rc == 1:
+        raise ValueError("mag_bins_overlap: non-finite magnitude")
+    return a, b
+
+
+def _overlap_bits(phase_overlap: bool, mag_overlap: bool) -> int:
+    return int(bool(phase_overlap)) | (int(bool(mag_overlap)) << 1)
+
+
 def fold_bin(dt: float, period: float, pdot: float, n_phase: int) -> int:
     """Phase bin of one epoch offset dt under Eq. (3)."""
     return int(_load().ce_oracle_fold_bin(float(dt), float(period), float(pdot),
@@ -119,16 +139,18 @@ def entropy(counts) -> float:
 
 
 def counts(times, mags, period: float, pdot: float, n_phase: int,
-           n_mag: int, phase_overlap: bool = False) -> np.ndarray:
+           n_mag: int, phase_overlap: bool = False,
+           mag_overlap: bool = False) -> np.ndarray:
     """[n_mag][n_phase] histogram of one curve at one (P, Pdot) trial
-    (each epoch counted twice with 50%-overlapping phase bins)."""
+    (each epoch counted in two phase bins with 50%-overlapping phase bins,
+    in one or two magnitude bins with 50%-overlapping magnitude bins)."""
     t, m = _f64(times), _f64(mags)
     if t.size != m.size:
         raise ValueError("times and mags differ in length")
     out = np.zeros((n_mag, n_phase), dtype=np.uint32)
     rc = _load().ce_oracle_counts(_p(t, _d), _p(m, _d), t.size, float(period),
-                                  float(pdot), n_phase, n_mag, int(phase_overlap),
-                                  _p(out, _u32))
+                                  float(pdot), n_phase, n_mag,
+                                  _overlap_bits(phase_overlap, mag_overlap), _p(out, _u32))
     _check(rc, "counts")
     if rc == 1:
         raise ValueError("counts: non-finite input")
@@ -136,7 +158,8 @@ def counts(times, mags, period: float, pdot: float, n_phase: int,
 
 
 def search(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
-           want_cube: bool = True, n_threads: int = 0, phase_overlap: bool = False):
+           want_cube: bool = True, n_threads: int = 0, phase_overlap: bool = False,
+           mag_overlap: bool = False):
     """Full grid search.  Returns (cube or None, best_flat, best_ce).
 
     cube is [n_curves][n_pdots][n_periods]; best_flat = q * n_periods + p.
@@ -150,7 +173,8 @@ def search(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
     bc = np.empty(nc)
     rc = _load().ce_oracle_search(_p(t, _d), _p(m, _d), _p(off, _i64), nc,
                                   _p(P, _d), P.size, _p(Pd, _d), Pd.size,
-                                  n_phase, n_mag, int(phase_overlap), _p(cube, _d),
+                                  n_phase, n_mag, _overlap_bits(phase_overlap, mag_overlap),
+                                  _p(cube, _d),
                                   _p(bf, _i64), _p(bc, _d), n_threads)
     _check(rc, "search")
     return cube, bf, bc
@@ -177,7 +201,7 @@ def search_ponly(times, mags, offsets, periods, n_phase: int, n_mag: int,
 
 def trials(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
            curve_ids, flat_ids, want_counts: bool = False, n_threads: int = 0,
-           phase_overlap: bool = False):
+           phase_overlap: bool = False, mag_overlap: bool = False):
     """H_c (and optionally counts) of selected (curve, flat) trials."""
     t, m = _f64(times), _f64(mags)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -190,8 +214,8 @@ def trials(times, mags, offsets, periods, pdots, n_phase: int, n_mag: int,
     cnt = np.empty((ci.size, n_mag, n_phase), dtype=np.uint32) if want_counts else None
     rc = _load().ce_oracle_trials(_p(t, _d), _p(m, _d), _p(off, _i64),
                                   off.size - 1, _p(P, _d), P.size, _p(Pd, _d),
-                                  Pd.size, n_phase, n_mag, int(phase_overlap),
-                                  _p(ci, _i64), _p(fi, _i64), ci.size, _p(ce, _d),
+                                  Pd.size, n_phase, n_mag,
+                                  _overlap_bits(phase_overlap, mag_overlap), _p(ci, _i64), _p(fi, _i64), ci.size, _p(ce, _d),
                                   _p(cnt, _u32), n_threads)
     _check(rc, "trials")
     return (ce, cnt) if want_counts else ce

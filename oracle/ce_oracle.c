@@ -19,6 +19,12 @@
  *     [0, 1] by their min and max and cut into n_mag equal-width bins; the
  *     median/std scaling of Sec. 2.3 is affine and so leaves these bins alone;
  *   - right edges (m = m_max, phase rounding up to 1) fall in the last bin;
+ *   - 50%-overlapping magnitude bins: the n_mag bins then have width
+ *     2 / (n_mag + 1) and start every 1 / (n_mag + 1), so they tile [0, 1]
+ *     with each bin sharing half of itself with each neighbour; an epoch in
+ *     the first or last half-bin is in one bin, every other epoch in two.
+ *     Probabilities of Eq. (4) are counts over the total count of the
+ *     histogram (the same divisor as N, or 2N, without magnitude overlap);
  *   - the phase bin is floor(phi * n_phase) of the exact product (the
  *     computed phase phi itself is the rounded fold of Eq. (3));
  *   - empty histogram cells contribute nothing to Eq. (4);
@@ -45,13 +51,21 @@
 
 /* ---------------------------------------------------------------------------
  * Sec. 2.3: magnitudes normalised per light curve, then binned into n_mag
- * equal-width magnitude bins.  Writes bin[k] in [0, n_mag).  Returns 0, or
- * ORACLE_EINVAL for n <= 0 / n_mag < 1, or 1 if a magnitude is not finite.
+ * magnitude bins.  u = (m - m_min) / (m_max - m_min) lies in [0, 1].
+ *   disjoint bins (overlap = 0): bin j is [j, j + 1) / n_mag, so the epoch
+ *     is in bin floor(u * n_mag); bin2 (if not NULL) is -1;
+ *   50%-overlapping bins (overlap = 1): bin j is [j, j + 2) / (n_mag + 1);
+ *     with s = floor(u * (n_mag + 1)) the epoch lies in the sub-interval
+ *     [s, s + 1) / (n_mag + 1), which belongs to bins s - 1 and s where
+ *     those exist: bin[k] is the lower of them, bin2[k] the other or -1.
+ * u = 1 (m = m_max) counts as inside the last sub-interval.  A constant curve
+ * has every epoch in bin 0 alone.  Returns 0, or ORACLE_EINVAL for n <= 0 /
+ * n_mag < 1 / overlap with bin2 NULL, or 1 if a magnitude is not finite.
  * ------------------------------------------------------------------------- */
-int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
-                       int32_t *bin)
+int ce_oracle_mag_bins2(const double *mags, int64_t n, int32_t n_mag,
+                        int32_t overlap, int32_t *bin, int32_t *bin2)
 {
-    if (n <= 0 || n_mag < 1 || !mags || !bin)
+    if (n <= 0 || n_mag < 1 || !mags || !bin || (overlap && !bin2))
         return ORACLE_EINVAL;
     double lo = mags[0], hi = mags[0];
     for (int64_t k = 0; k < n; ++k) {
@@ -61,16 +75,38 @@ int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
         if (mags[k] > hi) hi = mags[k];
     }
     for (int64_t k = 0; k < n; ++k) {
+        if (bin2)
+            bin2[k] = -1;
         if (hi == lo) {
             bin[k] = 0;          /* constant curve: one magnitude bin */
             continue;
         }
         double u = (mags[k] - lo) / (hi - lo); /* normalised to [0, 1] */
-        int32_t j = (int32_t)(u * (double)n_mag);
-        if (j >= n_mag) j = n_mag - 1;          /* m == m_max */
-        bin[k] = j;
+        if (!overlap) {
+            int32_t j = (int32_t)(u * (double)n_mag);
+            if (j >= n_mag) j = n_mag - 1;      /* m == m_max */
+            bin[k] = j;
+            continue;
+        }
+        int32_t s = (int32_t)(u * (double)(n_mag + 1)); /* sub-interval */
+        if (s > n_mag) s = n_mag;                       /* m == m_max */
+        if (s == 0) {                 /* first half-bin: bin 0 only */
+            bin[k] = 0;
+        } else if (s == n_mag) {      /* last half-bin: bin n_mag - 1 only */
+            bin[k] = n_mag - 1;
+        } else {                      /* bins s - 1 and s */
+            bin[k] = s - 1;
+            bin2[k] = s;
+        }
     }
     return ORACLE_OK;
+}
+
+/* Disjoint magnitude bins only (the original interface). */
+int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
+                       int32_t *bin)
+{
+    return ce_oracle_mag_bins2(mags, n, n_mag, 0, bin, NULL);
 }
 
 /* ---------------------------------------------------------------------------
@@ -164,17 +200,23 @@ typedef struct {
     int64_t n;
     double *dt;        /* t - t0 */
     int32_t *mbin;     /* magnitude bin of each epoch */
+    int32_t *mbin2;    /* second magnitude bin (overlapping bins) or -1 */
     int valid;
 } curve_prep;
 
+/* bits of the `overlap` arguments below */
+#define OVERLAP_PHASE 1
+#define OVERLAP_MAG 2
+
 static int prep_curve(const double *t, const double *m, int64_t n,
-                      int32_t n_mag, curve_prep *cp)
+                      int32_t n_mag, int overlap, curve_prep *cp)
 {
     cp->n = n;
     cp->valid = 1;
     cp->dt = (double *)malloc((size_t)n * sizeof(double));
     cp->mbin = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-    if (!cp->dt || !cp->mbin)
+    cp->mbin2 = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!cp->dt || !cp->mbin || !cp->mbin2)
         return ORACLE_ENOMEM;
     double t0 = t[0];
     for (int64_t k = 0; k < n; ++k) {
@@ -184,7 +226,8 @@ static int prep_curve(const double *t, const double *m, int64_t n,
     }
     for (int64_t k = 0; k < n; ++k)
         cp->dt[k] = t[k] - t0;
-    if (ce_oracle_mag_bins(m, n, n_mag, cp->mbin) != ORACLE_OK)
+    if (ce_oracle_mag_bins2(m, n, n_mag, (overlap & OVERLAP_MAG) != 0, cp->mbin,
+                            cp->mbin2) != ORACLE_OK)
         cp->valid = 0;
     return ORACLE_OK;
 }
@@ -193,15 +236,19 @@ static void free_prep(curve_prep *cp)
 {
     free(cp->dt);
     free(cp->mbin);
+    free(cp->mbin2);
     cp->dt = NULL;
     cp->mbin = NULL;
+    cp->mbin2 = NULL;
 }
 
 /* Histogram of one trial: counts[n_mag][n_phase] is cleared and filled.
- * With overlap, phase bin k spans [k, k + 2) / n_phase (wrapping), i.e. each
- * bin overlaps each neighbour by half (Sec. 2.3): an epoch whose phase lies in
- * [b, b + 1) / n_phase is inside bins b and b - 1 (mod n_phase), so every
- * epoch is counted twice and the counts total 2N. */
+ * With overlapping phase bins (bit OVERLAP_PHASE), phase bin k spans
+ * [k, k + 2) / n_phase (wrapping), i.e. each bin overlaps each neighbour by
+ * half (Sec. 2.3): an epoch whose phase lies in [b, b + 1) / n_phase is inside
+ * bins b and b - 1 (mod n_phase), so every epoch is counted in two phase bins.
+ * With overlapping magnitude bins (bit OVERLAP_MAG) an epoch is counted in
+ * each magnitude bin that contains it (one or two). */
 static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
                          int ponly, int overlap, int32_t n_phase, int32_t n_mag,
                          uint32_t *counts)
@@ -210,17 +257,22 @@ static void trial_counts(const curve_prep *cp, double inv_p, double half_pdot,
     for (int64_t k = 0; k < cp->n; ++k) {
         int32_t b = ponly ? fold_bin_ponly(cp->dt[k], inv_p, n_phase)
                           : fold_bin(cp->dt[k], inv_p, half_pdot, n_phase);
-        counts[(int64_t)cp->mbin[k] * n_phase + b] += 1;
-        if (overlap) {
-            int32_t prev = (b == 0) ? n_phase - 1 : b - 1;
-            counts[(int64_t)cp->mbin[k] * n_phase + prev] += 1;
+        int32_t prev = (b == 0) ? n_phase - 1 : b - 1;
+        int32_t mb[2] = {cp->mbin[k], cp->mbin2[k]};
+        for (int i = 0; i < 2; ++i) {
+            if (mb[i] < 0)
+                continue;
+            counts[(int64_t)mb[i] * n_phase + b] += 1;
+            if (overlap & OVERLAP_PHASE)
+                counts[(int64_t)mb[i] * n_phase + prev] += 1;
         }
     }
 }
 
 /* ---------------------------------------------------------------------------
  * Histogram of one (curve, P, Pdot) trial, as used by Eq. (4).
- * times/mags hold the curve's n epochs; counts is [n_mag][n_phase].
+ * times/mags hold the curve's n epochs; counts is [n_mag][n_phase];
+ * overlap holds the bits described at ce_oracle_search.
  * Returns 0, ORACLE_EINVAL, or 1 if the curve is invalid (non-finite data).
  * ------------------------------------------------------------------------- */
 int ce_oracle_counts(const double *times, const double *mags, int64_t n,
@@ -230,7 +282,7 @@ int ce_oracle_counts(const double *times, const double *mags, int64_t n,
     if (n <= 0 || n_phase < 1 || n_mag < 1 || !times || !mags || !counts)
         return ORACLE_EINVAL;
     curve_prep cp;
-    if (prep_curve(times, mags, n, n_mag, &cp) != ORACLE_OK) {
+    if (prep_curve(times, mags, n, n_mag, overlap, &cp) != ORACLE_OK) {
         free_prep(&cp);
         return ORACLE_ENOMEM;
     }
@@ -263,7 +315,8 @@ static int check_offsets(const int64_t *off, int64_t n_curves)
  *   best_ce          : [n_curves] H_c at best_flat
  *   ponly            : nonzero => classic P-only fold, pdots ignored (n_pd
  *                      is still the size of the q axis of out_ce)
- *   overlap          : nonzero => 50%-overlapping phase bins
+ *   overlap          : bit 0 (1): 50%-overlapping phase bins; bit 1 (2):
+ *                      50%-overlapping magnitude bins
  *   n_threads        : OpenMP threads over (curve, q); <= 0 = runtime default
  * The result does not depend on n_threads.
  * ------------------------------------------------------------------------- */
@@ -287,7 +340,7 @@ static int search_impl(const double *times, const double *mags,
     int rc = ORACLE_OK;
     for (int64_t c = 0; c < n_curves && rc == ORACLE_OK; ++c)
         rc = prep_curve(times + off[c], mags + off[c], off[c + 1] - off[c],
-                        n_mag, &cps[c]);
+                        n_mag, overlap, &cps[c]);
     /* A grid value that is not a finite positive period, or a non-finite
      * Pdot, invalidates every curve. */
     int grid_ok = 1;
@@ -447,6 +500,7 @@ int ce_oracle_trials(const double *times, const double *mags,
         int64_t cur = -1;
         cp.dt = NULL;
         cp.mbin = NULL;
+        cp.mbin2 = NULL;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t t = 0; t < n_trials; ++t) {
             if (!counts) {
@@ -458,7 +512,8 @@ int ce_oracle_trials(const double *times, const double *mags,
             if (c != cur) {
                 free_prep(&cp);
                 if (prep_curve(times + off[c], mags + off[c],
-                               off[c + 1] - off[c], n_mag, &cp) != ORACLE_OK) {
+                               off[c + 1] - off[c], n_mag, overlap,
+                               &cp) != ORACLE_OK) {
 #pragma omp atomic write
                     fail = 1;
                     cur = -1;

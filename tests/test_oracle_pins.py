@@ -456,3 +456,122 @@ def test_overlap_search_consistent_with_counts():
             cnt = oracle.counts(t, m, w.periods[p], w.pdots[q], 10, 5, phase_overlap=True)
             assert cnt.sum() == 2 * t.size
             assert abs(oracle.entropy(cnt) - cube[c, q, p]) == 0.0
+
+
+# --------------------------------------------------------------------------
+# 50%-overlapping magnitude bins (Sec. 2.3)
+# --------------------------------------------------------------------------
+def _mag_bins_by_membership(u, n_mag):
+    """Bins j whose interval [j, j + 2) / (n_mag + 1) holds the exact u
+    (u = 1 belongs to the last bin), from exact rationals."""
+    u = Fraction(u)
+    w = Fraction(1, n_mag + 1)
+    if n_mag == 1:
+        return [0]
+    got = [j for j in range(n_mag) if j * w <= u < (j + 2) * w]
+    if u == 1:
+        got = [n_mag - 1]
+    return got
+
+
+@pytest.mark.parametrize("n_mag", [1, 2, 3, 5, 7, 10])
+def test_mag_overlap_bins_by_interval_membership(n_mag):
+    """Magnitudes k / 256 with minimum 0 and maximum 1: the normalised value
+    and its product with n_mag + 1 are exact, so the bins are fixed by
+    interval membership alone, edges included."""
+    m = np.arange(257) / 256.0
+    a, b = oracle.mag_bins_overlap(m, n_mag)
+    for k in range(257):
+        want = _mag_bins_by_membership(Fraction(k, 256), n_mag)
+        got = [int(a[k])] + ([int(b[k])] if b[k] >= 0 else [])
+        assert got == want, (k, n_mag)
+
+
+def test_mag_overlap_bins_invariants():
+    rng = np.random.default_rng(44)
+    m = rng.normal(size=500)
+    for n_mag in (2, 3, 5, 10, 255):
+        a, b = oracle.mag_bins_overlap(m, n_mag)
+        assert a.min() == 0 and a.max() == n_mag - 1
+        two = b >= 0
+        assert np.all(b[two] == a[two] + 1)          # neighbours only
+        assert a[np.argmin(m)] == 0 and b[np.argmin(m)] == -1
+        assert a[np.argmax(m)] == n_mag - 1 and b[np.argmax(m)] == -1
+        order = np.argsort(m, kind="stable")
+        assert np.all(np.diff(a[order]) >= 0)       # monotone in magnitude
+        # each bin is one contiguous run of magnitudes that overlaps its
+        # neighbour's run: in the sorted order, bin j's members end after
+        # bin j + 1's begin (when both have two or more members)
+        for j in range(n_mag - 1):
+            mj = np.flatnonzero((a[order] == j) | (b[order] == j))
+            mn = np.flatnonzero((a[order] == j + 1) | (b[order] == j + 1))
+            if mj.size and mn.size:
+                assert np.all(np.diff(mj) == 1) and mj[-1] >= mn[0] - 1
+    # a constant curve: bin 0 alone
+    a, b = oracle.mag_bins_overlap(np.full(7, 3.5), 4)
+    assert np.all(a == 0) and np.all(b == -1)
+
+
+@pytest.mark.parametrize("phase_overlap", [False, True])
+@pytest.mark.parametrize("n_mag", [1, 3, 4])
+def test_mag_overlap_counts_by_interval_membership(n_mag, phase_overlap):
+    """Every (epoch, magnitude bin, phase bin) membership from exact
+    rationals; H from the library Shannon entropy of the counts."""
+    n_phase = 8
+    t, m, off, periods, pdots = _dyadic_workload(60 + n_mag, n_curves=2, n_points=40)
+    for c in range(2):
+        tc, mc = t[off[c]:off[c + 1]], m[off[c]:off[c + 1]]
+        dt = tc - tc.min()
+        for P in periods[:3]:
+            for Pd in pdots:
+                want = np.zeros((n_mag, n_phase), dtype=np.int64)
+                for d, u in zip(dt, mc):
+                    phi = _exact_phase(d, P, Pd)
+                    for j in _mag_bins_by_membership(u, n_mag):
+                        for k in range(n_phase):
+                            rel = (phi - Fraction(k, n_phase)) % 1
+                            inside = (rel < Fraction(2, n_phase)) if phase_overlap \
+                                else (rel < Fraction(1, n_phase))
+                            want[j, k] += int(inside)
+                got = oracle.counts(tc, mc, P, Pd, n_phase, n_mag,
+                                    phase_overlap=phase_overlap, mag_overlap=True)
+                assert np.array_equal(got, want), (c, P, Pd)
+                assert abs(oracle.entropy(got) - _conditional_entropy_scipy(want)) <= 1e-13
+
+
+def test_mag_overlap_single_bin_is_disjoint():
+    """With one magnitude bin the overlapping layout is the disjoint one."""
+    w = synth.random_curves(45, [30, 90], n_freq=30, n_pdots=2)
+    for po in (False, True):
+        a = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 1,
+                          phase_overlap=po)
+        b = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 1,
+                          phase_overlap=po, mag_overlap=True)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_mag_overlap_search_consistent_with_counts():
+    w = synth.random_curves(46, [30, 200], n_freq=40, n_pdots=3)
+    for po in (False, True):
+        cube, bf, bc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                     10, 5, phase_overlap=po, mag_overlap=True)
+        ids = np.arange(w.periods.size * w.pdots.size)
+        for c in range(2):
+            h = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                              np.full(ids.size, c), ids, phase_overlap=po,
+                              mag_overlap=True)
+            assert np.array_equal(h, cube[c].ravel())
+            t, m = w.curve(c)
+            a, b = oracle.mag_bins_overlap(m, 5)
+            entries = t.size + int((b >= 0).sum())
+            for f in (0, 17, ids.size - 1):
+                q, p = divmod(int(f), w.periods.size)
+                cnt = oracle.counts(t, m, w.periods[p], w.pdots[q], 10, 5,
+                                    phase_overlap=po, mag_overlap=True)
+                assert cnt.sum() == (2 if po else 1) * entries
+                # the magnitude marginal does not depend on the trial
+                rows = np.bincount(a, minlength=5) + np.bincount(b[b >= 0], minlength=5)
+                assert np.array_equal(cnt.sum(axis=1), (2 if po else 1) * rows)
+                assert oracle.entropy(cnt) == cube[c, q, p]
+            assert bf[c] == int(np.argmin(cube[c].ravel()))
