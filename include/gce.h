@@ -17,13 +17,15 @@
  * ---------------------------------------
  *  - Units: epochs and periods in days, Pdot dimensionless.
  *  - t0 is the earliest epoch of each curve.  Magnitudes are normalised per
- *    curve onto [0, 1] by their minimum and maximum and cut into n_mag equal
- *    bins (the maximum falls in the last bin; a constant curve has one bin).
+ *    curve onto [0, 1] by their minimum and maximum (u = (m - min) / (max -
+ *    min), correctly rounded) and cut into n_mag equal bins, bin
+ *    min((int)(u * n_mag), n_mag - 1) (the maximum falls in the last bin; a
+ *    constant curve has one bin).
  *  - Fold arithmetic is IEEE binary64 in this order: invP = 1.0 / P
  *    (correctly rounded), x = dt * invP, x2 = x * x,
- *    y = fma(-(0.5 * Pdot), x2, x), phi = y - floor(y),
- *    phase bin = min((int)(phi * n_phase), n_phase - 1).  The FP64 path
- *    reproduces these bins bit for bit.
+ *    y = fma(-(0.5 * Pdot), x2, x), phi = y - floor(y); the phase bin is the
+ *    floor of the exact product phi * n_phase (not of its rounding), at most
+ *    n_phase - 1.  The FP64 path reproduces these bins bit for bit.
  *  - Curves are ragged: epochs of curve c occupy [offsets[c], offsets[c+1])
  *    of the concatenated `times` / `mags` arrays.
  *  - The CE cube is row-major [curve][pdot][period] (period fastest); the
@@ -43,7 +45,8 @@
  *    curves (all curves for a bad grid) get flat_index = -1, ce_min = NaN and
  *    NaN CE values.
  *  - Limits: 1 <= n_phase_bins <= 128, 1 <= n_mag_bins <= 255,
- *    1 <= points per curve <= 65535 (counts are 16-bit).
+ *    1 <= points per curve <= 65535 (counts are 16-bit; overlapping bins
+ *    that count an epoch twice halve this, see gce_opts).
  */
 #ifndef GCE_H
 #define GCE_H
@@ -123,6 +126,18 @@ typedef struct {
                                 0 = automatic, 1 = global memory, 2 = a copy in
                                 each wave's LDS (pays off when there are many
                                 histogram cells per epoch) */
+    int32_t mag_overlap;     /* nonzero: 50%-overlapping magnitude bins (Sec.
+                                2.3): bin j spans [j, j + 2) / (n_mag + 1) of
+                                the normalised magnitude u, i.e. with
+                                s = min((int)(u * (n_mag + 1)), n_mag) the
+                                epoch is in bins s - 1 and s where they exist
+                                (one bin in the first and last half-bin).  The
+                                probabilities of Eq. (4) are counts over the
+                                histogram's total count.  Curves may then hold
+                                at most 32767 epochs (4095 with the table in
+                                LDS); with phase_overlap and n_phase_bins = 1
+                                the limits halve again (GCE_EUNSUPPORTED
+                                beyond them). */
 } gce_opts;
 
 #define GCE_TABLE_AUTO 0
@@ -136,6 +151,7 @@ typedef struct {
  *  plan          : out, the new plan.
  *  curve_offsets : HOST, [n_curves + 1] as for gce_search (copied).
  *  opts          : may be NULL (FP64, automatic tiling, disjoint bins).
+ *                  Zero-initialise it and set the fields wanted.
  *  device        : HIP device ordinal the plan runs on.
  */
 int gce_plan_create(gce_plan_t *plan, const int64_t *curve_offsets,
@@ -228,7 +244,7 @@ int gce_merge_results(gce_best_t *acc, int64_t acc_trials,
  * gce_autotune -- measure the search kernel's tilings -- Pdot trials per
  * lane (1, 2, 4, 8) and c ln c table placement (global, LDS), those that fit
  * in LDS -- on a slice of the given workload and remember the fastest for
- * its shape class: precision, overlap, phase and
+ * its shape class: precision, phase and magnitude overlap, phase and
  * magnitude bin counts, Pdot count (1, 2, 3-4, 5-8, more) and median curve
  * length (<128, <512, <2048, more).  Later plans created with automatic tiling
  * (trials_per_lane = 0) in this process use the remembered choice.  If the
@@ -248,9 +264,9 @@ int gce_autotune(const double *times, const double *mags,
                  const int64_t *curve_offsets, int64_t n_curves,
                  const double *periods, int64_t n_periods, const double *pdots,
                  int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
-                 int32_t precision, int32_t phase_overlap, int32_t device,
-                 void *stream, int32_t *best_tq, int32_t *best_placement,
-                 float *ms);
+                 int32_t precision, int32_t phase_overlap, int32_t mag_overlap,
+                 int32_t device, void *stream, int32_t *best_tq,
+                 int32_t *best_placement, float *ms);
 
 /* Bytes of device workspace the plan holds. */
 size_t gce_plan_workspace_bytes(gce_plan_t plan);

@@ -54,7 +54,8 @@ class _Info(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
-                ("phase_overlap", ctypes.c_int32), ("table_placement", ctypes.c_int32)]
+                ("phase_overlap", ctypes.c_int32), ("table_placement", ctypes.c_int32),
+                ("mag_overlap", ctypes.c_int32)]
 
 
 _lib = None
@@ -89,7 +90,7 @@ def lib():
         L.gce_plan_get_info.argtypes = [_vp, ctypes.POINTER(_Info)]
         L.gce_merge_results.argtypes = [_vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _i64]
         L.gce_autotune.argtypes = [_vp, _vp, ctypes.POINTER(_i64), _i64, _vp, _i64, _vp, _i64,
-                                   _i32, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32),
+                                   _i32, _i32, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32),
                                    ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]
         L.gce_plan_search_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), _i32,
                                             ctypes.POINTER(_i32)]
@@ -150,7 +151,7 @@ class Plan:
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
                  trials_per_lane: int = 0, phase_overlap: bool = False,
-                 table_placement: int = TABLE_AUTO,
+                 table_placement: int = TABLE_AUTO, mag_overlap: bool = False,
                  device: Optional[torch.device] = None):
         self._h = None
         self.offsets = _host_offsets(offsets)
@@ -163,8 +164,9 @@ class Plan:
             idx = torch.cuda.current_device() if torch.cuda.is_available() else 0
             self.device = torch.device("cuda", idx)
         self.phase_overlap = bool(phase_overlap)
+        self.mag_overlap = bool(mag_overlap)
         opts = _Opts(self.precision, int(trials_per_lane), int(self.phase_overlap),
-                     int(table_placement))
+                     int(table_placement), int(self.mag_overlap))
         h = ctypes.c_void_p()
         L = lib()
         _check(L.gce_plan_create(ctypes.byref(h),
@@ -265,7 +267,8 @@ class Plan:
 
 def autotune(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Tensor,
              pdots: torch.Tensor, n_phase: int, n_mag: int,
-             precision: int = PRECISION_FP64, phase_overlap: bool = False, stream=None):
+             precision: int = PRECISION_FP64, phase_overlap: bool = False,
+             mag_overlap: bool = False, stream=None):
     """Time the tilings (trials per lane x table placement) on a slice of this
     workload and remember the fastest for its shape class (gce_autotune).
     Returns (chosen trials per lane, chosen placement,
@@ -281,7 +284,7 @@ def autotune(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Te
                               off.ctypes.data_as(ctypes.POINTER(_i64)), off.size - 1,
                               _ptr(periods), periods.numel(), _ptr(pdots), pdots.numel(),
                               int(n_phase), int(n_mag), int(precision), int(phase_overlap),
-                              device.index or 0, _stream_handle(stream, device),
+                              int(mag_overlap), device.index or 0, _stream_handle(stream, device),
                               ctypes.byref(tq), ctypes.byref(placement), ms))
     keys = [(t, pl) for pl in (TABLE_GLOBAL, TABLE_LDS) for t in (1, 2, 4, 8)]
     return tq.value, placement.value, {k: float(v) for k, v in zip(keys, ms) if v >= 0}

@@ -109,6 +109,7 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
                    chunk_periods: int, checkpoint: Optional[str] = None,
                    precision: int = 0, phase_overlap: bool = False,
                    trials_per_lane: int = 0, table_placement: int = 0,
+                   mag_overlap: bool = False,
                    want_cube: bool = False, on_range: Optional[Callable] = None,
                    stream=None) -> np.ndarray:
     """Minimum and statistics of every curve over the full (P, Pdot) grid,
@@ -128,7 +129,7 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
             x.detach().cpu().numpy() for x in (times, mags, periods, pdots)]
         fp = fingerprint(host, n_phase=int(n_phase), n_mag=int(n_mag),
                          precision=int(precision), phase_overlap=bool(phase_overlap),
-                         chunk=int(chunk_periods))
+                         mag_overlap=bool(mag_overlap), chunk=int(chunk_periods))
     plans = {}
 
     def execute_range(p0, p1):
@@ -136,7 +137,8 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
         if n not in plans:
             plans[n] = Plan(offsets, n, n_pd, n_phase, n_mag, precision=precision,
                             trials_per_lane=trials_per_lane, phase_overlap=phase_overlap,
-                            table_placement=table_placement, device=times.device)
+                            table_placement=table_placement, mag_overlap=mag_overlap,
+                            device=times.device)
         plan = plans[n]
         cube = plan.new_cube() if want_cube else None
         cube, best = plan.execute(times, mags, periods[p0:p1], pdots, out_ce=cube,

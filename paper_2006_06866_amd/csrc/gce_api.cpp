@@ -75,7 +75,7 @@ int check_device(int dev)
 // ---------------------------------------------------------------------------
 // tiling choice: autotuned per shape class, else a measured heuristic
 // ---------------------------------------------------------------------------
-// prec, overlap, nph, nmag, pd class, N class
+// prec, overlap bits (1 phase, 2 magnitude), nph, nmag, pd class, N class
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 
 struct Tiling {
@@ -128,22 +128,22 @@ void read_tune_file_locked()
             g_tuned[TuneKey{a, b, c, d, e, f}] = Tiling{tq, ll};
 }
 
-// The table in LDS costs every wave one pass over max_n + 1 doubles and
+// The table in LDS costs every wave one pass over max_count + 1 doubles and
 // LDS space, and saves a global gather per histogram cell at every
 // magnitude-segment flush: it pays when the table is small, the cells are
 // many per epoch, and the wave's LDS stays small enough for 8 or more
 // waves per CU.  Measured on MI355X: 50 x 10 overlapping bins, N = 500,
 // 2 trials: 4.9 s with the table in LDS vs 6.5 s; 10 x 5 bins, N = 600:
 // 75 vs 61 ms; N up to 3,000: 485 vs 209 ms.
-int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max_n,
+int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max_count,
                       int64_t median_n)
 {
-    return max_n <= 1023 && 4 * (int64_t)n_phase * n_mag >= median_n &&
-           gce::search_lds_bytes(precision, n_phase, tq, 1, max_n) <=
+    return max_count <= 1023 && 4 * (int64_t)n_phase * n_mag >= median_n &&
+           gce::search_lds_bytes(precision, n_phase, tq, 1, max_count) <=
                (size_t)gce::search_waves_per_block(1) * 20 * 1024;
 }
 
-int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
+int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
 {
     // Pdot trials per lane: more trials share each epoch's x and x^2, but
     // every trial pair adds a histogram region of LDS and registers.
@@ -157,7 +157,7 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
     int tq = precision == GCE_PRECISION_FP64 ? 4 : 8;
     while (tq > 1 &&
            (tq >= 2 * n_pd || !gce::search_variant_exists(precision, n_phase, tq) ||
-            gce::search_lds_bytes(precision, n_phase, tq, 0, max_n) > 13 * 1024))
+            gce::search_lds_bytes(precision, n_phase, tq, 0, max_count) > 13 * 1024))
         tq /= 2;
     return tq;
 }
@@ -166,7 +166,7 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_n)
 // trials per lane nor the table placement is requested, else the request
 // and the heuristics for what was left open.
 Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
-                     const int64_t *off, int64_t n_curves, int32_t max_n,
+                     const int64_t *off, int64_t n_curves, int32_t max_count,
                      int requested_tq, int requested_placement)
 {
     if (requested_tq == 0 && requested_placement == GCE_TABLE_AUTO) {
@@ -179,10 +179,10 @@ Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t
             return it->second;
     }
     Tiling t{0, 0};
-    t.tq = requested_tq > 0 ? requested_tq : heuristic_tq(precision, n_phase, n_pd, max_n);
+    t.tq = requested_tq > 0 ? requested_tq : heuristic_tq(precision, n_phase, n_pd, max_count);
     if (requested_placement == GCE_TABLE_GLOBAL) t.lut_lds = 0;
     else if (requested_placement == GCE_TABLE_LDS) t.lut_lds = 1;
-    else t.lut_lds = heuristic_lut_lds(precision, n_phase, n_mag, t.tq, max_n,
+    else t.lut_lds = heuristic_lut_lds(precision, n_phase, n_mag, t.tq, max_count,
                                        median_length(off, n_curves));
     return t;
 }
@@ -248,6 +248,30 @@ int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
     return GCE_OK;
 }
 
+// Largest count a histogram cell, a marginal or a pair of phase slots can
+// reach: every entry of a curve lands in one cell per phase slot, a curve has
+// up to 2N entries with overlapping magnitude bins, and a single overlapping
+// phase bin adds its one slot to itself.  Counts are 16-bit, so the bound must
+// stay at or below 65535.
+int count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap, int32_t mag_overlap,
+                int32_t *max_count_out)
+{
+    int64_t m = max_n;
+    if (mag_overlap) m *= 2;
+    if (phase_overlap && n_phase == 1) m *= 2;
+    if (m > gce::kMaxPoints)
+        return fail(GCE_EUNSUPPORTED,
+                    "overlapping bins count an epoch more than once: the counts of "
+                    "the longest curve would exceed 65535");
+    *max_count_out = (int32_t)m;
+    return GCE_OK;
+}
+
+int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
+{
+    return (phase_overlap ? 1 : 0) | (mag_overlap ? 2 : 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -295,18 +319,26 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         return fail(GCE_EINVAL, "trials_per_lane must be 0, 1, 2, 4 or 8");
     if (o.phase_overlap != 0 && o.phase_overlap != 1)
         return fail(GCE_EINVAL, "phase_overlap must be 0 or 1");
+    if (o.mag_overlap != 0 && o.mag_overlap != 1)
+        return fail(GCE_EINVAL, "mag_overlap must be 0 or 1");
     if (o.table_placement != GCE_TABLE_AUTO && o.table_placement != GCE_TABLE_GLOBAL &&
         o.table_placement != GCE_TABLE_LDS)
         return fail(GCE_EINVAL, "table_placement must be 0, 1 or 2");
-    const Tiling tl = choose_tiling(o.precision, o.phase_overlap, n_phase_bins, n_mag_bins,
-                                    n_pdots, curve_offsets, n_curves, max_n,
-                                    o.trials_per_lane, o.table_placement);
+    int32_t max_count = 0;
+    rc = count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
+    if (rc != GCE_OK) return rc;
+    const Tiling tl = choose_tiling(o.precision, overlap_bits(o.phase_overlap, o.mag_overlap),
+                                    n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
+                                    n_curves, max_count, o.trials_per_lane,
+                                    o.table_placement);
     const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
-    if (tl.lut_lds && max_n > 8191)   // LDS-table counts are kept in units of 8
-        return fail(GCE_EUNSUPPORTED, "the table in LDS needs curves of at most 8191 epochs");
-    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_n) > 64 * 1024)
+    if (tl.lut_lds && max_count > 8191)   // LDS-table counts are kept in units of 8
+        return fail(GCE_EUNSUPPORTED,
+                    "the table in LDS needs counts of at most 8191 (curves of at most "
+                    "8191 epochs, half that with overlapping magnitude bins)");
+    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_count) > 64 * 1024)
         return fail(GCE_EUNSUPPORTED,
                     "a wave's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
                     "table in global memory");
@@ -335,9 +367,10 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.n_ptiles = (n_periods + gce::kWave - 1) / gce::kWave;
     dp.units_per_curve = (int64_t)dp.n_qgroups * dp.n_ptiles;
     dp.n_units = n_curves * dp.units_per_curve;
-    dp.max_n = max_n;
+    dp.max_count = max_count;
     dp.precision = o.precision;
     dp.overlap = o.phase_overlap;
+    dp.mag_overlap = o.mag_overlap;
     dp.lut_lds = tl.lut_lds;
     if (dp.n_units > gce::kMaxUnits) {
         delete pl;
@@ -362,9 +395,10 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     };
     const size_t o_off = take(sizeof(int64_t) * (size_t)(n_curves + 1));
     const size_t o_order = take(sizeof(int32_t) * (size_t)n_curves);
-    const size_t o_lut = take(sizeof(double) * (size_t)(max_n + 1));
-    const size_t o_lut32 = take(sizeof(float) * (size_t)(max_n + 1));
-    const size_t o_dt = take(sizeof(double) * (size_t)pl->total_points);
+    const size_t o_lut = take(sizeof(double) * (size_t)(max_count + 1));
+    const size_t o_lut32 = take(sizeof(float) * (size_t)(max_count + 1));
+    const size_t o_dt = take(sizeof(double) * (size_t)pl->total_points *
+                             (o.mag_overlap ? 2 : 1));
     const size_t o_seg = take(sizeof(int32_t) * (size_t)n_curves * (size_t)(n_mag_bins + 1));
     const size_t o_cok = take(sizeof(int32_t) * (size_t)n_curves);
     const size_t o_gok = take(sizeof(int32_t));
@@ -526,7 +560,7 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
     info->trials_per_lane = pl->dp.tq;
     info->lds_bytes_per_wave = (int32_t)(
         gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds,
-                              pl->dp.max_n) /
+                              pl->dp.max_count) /
         gce::search_waves_per_block(pl->dp.lut_lds));
     info->table_in_lds = pl->dp.lut_lds;
     info->work_units = pl->dp.n_units;
@@ -675,9 +709,9 @@ extern "C" int gce_autotune(const double *times, const double *mags,
                             const double *periods, int64_t n_periods,
                             const double *pdots, int64_t n_pdots,
                             int32_t n_phase_bins, int32_t n_mag_bins,
-                            int32_t precision, int32_t phase_overlap, int32_t device,
-                            void *stream, int32_t *best_tq, int32_t *best_placement,
-                            float *ms)
+                            int32_t precision, int32_t phase_overlap,
+                            int32_t mag_overlap, int32_t device, void *stream,
+                            int32_t *best_tq, int32_t *best_placement, float *ms)
 {
     int32_t max_n = 0;
     int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots, n_phase_bins,
@@ -689,6 +723,11 @@ extern "C" int gce_autotune(const double *times, const double *mags,
         return fail(GCE_EINVAL, "unknown precision");
     if (phase_overlap != 0 && phase_overlap != 1)
         return fail(GCE_EINVAL, "phase_overlap must be 0 or 1");
+    if (mag_overlap != 0 && mag_overlap != 1)
+        return fail(GCE_EINVAL, "mag_overlap must be 0 or 1");
+    int32_t max_count = 0;
+    rc = count_bound(max_n, n_phase_bins, phase_overlap, mag_overlap, &max_count);
+    if (rc != GCE_OK) return rc;
     rc = check_device(device);
     if (rc != GCE_OK) return rc;
     DeviceGuard guard(device);
@@ -736,12 +775,13 @@ extern "C" int gce_autotune(const double *times, const double *mags,
         const int tq = cands[ci % 4], ll = ci / 4;
         if (tq > 1 && tq >= 2 * n_pdots) continue;
         if (!gce::search_variant_exists(precision, n_phase_bins, tq) ||
-            gce::search_lds_bytes(precision, n_phase_bins, tq, ll, max_n) > 40 * 1024)
+            gce::search_lds_bytes(precision, n_phase_bins, tq, ll, max_count) > 40 * 1024)
             continue;
         gce_opts o{};
         o.precision = precision;
         o.trials_per_lane = tq;
         o.phase_overlap = phase_overlap;
+        o.mag_overlap = mag_overlap;
         o.table_placement = ll ? GCE_TABLE_LDS : GCE_TABLE_GLOBAL;
         gce_plan_t pl = nullptr;
         rc = gce_plan_create(&pl, off.data(), k, np_slice, n_pdots, n_phase_bins,
@@ -777,7 +817,8 @@ extern "C" int gce_autotune(const double *times, const double *mags,
     if (chosen.tq == 0) return fail(GCE_EUNSUPPORTED, "no tiling fits this shape");
     *best_tq = chosen.tq;
     if (best_placement) *best_placement = chosen.lut_lds ? GCE_TABLE_LDS : GCE_TABLE_GLOBAL;
-    const TuneKey key = tune_key(precision, phase_overlap, n_phase_bins, n_mag_bins, n_pdots,
+    const int ovl = overlap_bits(phase_overlap, mag_overlap);
+    const TuneKey key = tune_key(precision, ovl, n_phase_bins, n_mag_bins, n_pdots,
                                  curve_offsets, n_curves);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     read_tune_file_locked();
@@ -785,7 +826,7 @@ extern "C" int gce_autotune(const double *times, const double *mags,
     if (const char *path = std::getenv("GCE_TUNE_CACHE")) {
         if (*path) {
             std::ofstream out(path, std::ios::app);
-            out << precision << ' ' << phase_overlap << ' ' << n_phase_bins << ' '
+            out << precision << ' ' << ovl << ' ' << n_phase_bins << ' '
                 << n_mag_bins << ' ' << pdot_class(n_pdots) << ' '
                 << length_class(curve_offsets, n_curves) << ' ' << chosen.tq << ' '
                 << chosen.lut_lds << '\n';

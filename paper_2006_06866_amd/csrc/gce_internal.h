@@ -51,19 +51,25 @@ struct DevPlan {
     int64_t n_ptiles;         // ceil(n_p / 64)
     int64_t units_per_curve;  // n_qgroups * n_ptiles
     int64_t n_units;          // n_curves * units_per_curve
-    int32_t max_n;            // longest curve
+    int32_t max_count;        // largest count of a histogram cell, a marginal
+                              // or a pair of phase slots: the longest curve,
+                              // doubled with overlapping magnitude bins and
+                              // again for one overlapping phase bin
     int32_t precision;
     int32_t overlap;          // 50%-overlapping phase bins
+    int32_t mag_overlap;      // 50%-overlapping magnitude bins: each curve's
+                              // sorted-epoch region has room for 2N entries
     int32_t lut_lds;          // c ln c table copied into LDS by each wave
 
     // plan-time metadata
     const int64_t *off;       // [n_curves + 1] curve offsets
     const int32_t *order;     // [n_curves] schedule rank -> curve
-    const double *lut;        // [max_n + 1] c * ln(c)
-    const float *lut32;       // [max_n + 1] c * ln(c), float
+    const double *lut;        // [max_count + 1] c * ln(c)
+    const float *lut32;       // [max_count + 1] c * ln(c), float
 
     // per-execution scratch
-    double *dt_sorted;        // [total] t - t0, grouped by magnitude bin
+    double *dt_sorted;        // [total] t - t0, grouped by magnitude bin; curve
+                              // c at off[c] (2 off[c] with mag_overlap)
     int32_t *seg;             // [n_curves][n_mag + 1] segment starts
     int32_t *curve_ok;        // [n_curves]
     int32_t *grid_ok;         // [1]
@@ -111,8 +117,8 @@ bool search_variant_exists(int precision, int n_phase, int tq);
 // c ln c table.
 constexpr int kLutWaves = 2;
 inline int search_waves_per_block(int lut_lds) { return lut_lds ? kLutWaves : 1; }
-// Bytes of LDS one search block uses (lut_lds: the c ln c table of max_n + 1
-// entries is kept in LDS too, once per block).
-size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_n);
+// Bytes of LDS one search block uses (lut_lds: the c ln c table of
+// max_count + 1 entries is kept in LDS too, once per block).
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count);
 
 }  // namespace gce

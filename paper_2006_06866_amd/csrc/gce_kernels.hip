@@ -15,10 +15,10 @@ namespace gce {
 // ---------------------------------------------------------------------------
 // c ln c table
 // ---------------------------------------------------------------------------
-__global__ void k_lut(double *lut, float *lut32, int32_t max_n)
+__global__ void k_lut(double *lut, float *lut32, int32_t max_count)
 {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > max_n) return;
+    if (c > max_count) return;
     const double v = (c == 0) ? 0.0 : (double)c * log((double)c);
     lut[c] = v;
     lut32[c] = (float)v;
@@ -26,10 +26,10 @@ __global__ void k_lut(double *lut, float *lut32, int32_t max_n)
 
 hipError_t launch_lut(const DevPlan &dp, hipStream_t s)
 {
-    const int n = dp.max_n + 1;
+    const int n = dp.max_count + 1;
     hipLaunchKernelGGL(k_lut, dim3((n + 255) / 256), dim3(256), 0, s,
                        const_cast<double *>(dp.lut),
-                       const_cast<float *>(dp.lut32), dp.max_n);
+                       const_cast<float *>(dp.lut32), dp.max_count);
     return hipGetLastError();
 }
 
@@ -98,10 +98,36 @@ __device__ __forceinline__ double block_reduce(double v, bool is_min,
     return r;
 }
 
+// Magnitude bins of one epoch from its normalised magnitude u in [0, 1]
+// (Sec. 2.3).  Disjoint bins: bin j is [j, j + 1) / n_mag.  50%-overlapping
+// bins: bin j is [j, j + 2) / (n_mag + 1), so the sub-interval
+// s = floor(u (n_mag + 1)) belongs to bins s - 1 and s where they exist.  The
+// top edge u = 1 belongs to the last bin.  `second` is kNoBin unless the
+// epoch lies in two bins.
+constexpr uint8_t kNoBin = 255;   // n_mag <= 255: bins are 0..254
+struct MagBins {
+    int32_t first, second;
+};
+
+__device__ __forceinline__ MagBins magnitude_bins(double u, int32_t n_mag, bool overlap)
+{
+    if (!overlap) {
+        int32_t j = (int32_t)(u * (double)n_mag);
+        if (j >= n_mag) j = n_mag - 1;
+        return MagBins{j, kNoBin};
+    }
+    int32_t s = (int32_t)(u * (double)(n_mag + 1));
+    if (s > n_mag) s = n_mag;
+    if (s == 0) return MagBins{0, kNoBin};
+    if (s == n_mag) return MagBins{n_mag - 1, kNoBin};
+    return MagBins{s - 1, s};
+}
+
 __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     DevPlan dp, const double *__restrict__ times, const double *__restrict__ mags)
 {
     __shared__ uint8_t jb[kPrepChunk];
+    __shared__ uint8_t jb2[kPrepChunk];   // second bin (overlapping bins)
     __shared__ int32_t cnt[kMaxMagBins + 1];
     __shared__ int32_t cur[kMaxMagBins + 1];
     __shared__ double red[kPrepBlock / kWave];
@@ -140,15 +166,17 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     const double t0 = tmin;
     const bool flat_mag = !(mhi > mlo);
 
-    // magnitude bin of every epoch; counts per bin
+    // magnitude bins of every epoch (a constant or invalid curve has one
+    // bin); entries per bin
+    const bool movl = dp.mag_overlap != 0;
+    auto bins_of = [&](int32_t k) -> MagBins {
+        if (!ok || flat_mag) return MagBins{0, kNoBin};
+        return magnitude_bins((m[k] - mlo) / (mhi - mlo), n_mag, movl);
+    };
     for (int32_t k = threadIdx.x; k < n; k += kPrepBlock) {
-        int32_t j = 0;
-        if (ok && !flat_mag) {
-            const double u = (m[k] - mlo) / (mhi - mlo);
-            j = (int32_t)(u * (double)n_mag);
-            if (j >= n_mag) j = n_mag - 1;
-        }
-        atomicAdd(&cnt[j], 1);
+        const MagBins mb = bins_of(k);
+        atomicAdd(&cnt[mb.first], 1);
+        if (mb.second != kNoBin) atomicAdd(&cnt[mb.second], 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -164,25 +192,22 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     }
     __syncthreads();
 
-    // stable scatter of dt = t - t0 into magnitude-bin order, in chunks
-    double *dst = dp.dt_sorted + base;
+    // stable scatter of dt = t - t0 into magnitude-bin order, in chunks; an
+    // epoch in two bins is written into both segments
+    double *dst = dp.dt_sorted + (movl ? 2 * base : base);
     for (int32_t k0 = 0; k0 < n; k0 += kPrepChunk) {
         const int32_t k1 = min(n, k0 + kPrepChunk);
         for (int32_t k = k0 + threadIdx.x; k < k1; k += kPrepBlock) {
-            int32_t j = 0;
-            if (ok && !flat_mag) {
-                const double u = (m[k] - mlo) / (mhi - mlo);
-                j = (int32_t)(u * (double)n_mag);
-                if (j >= n_mag) j = n_mag - 1;
-            }
-            jb[k - k0] = (uint8_t)j;
+            const MagBins mb = bins_of(k);
+            jb[k - k0] = (uint8_t)mb.first;
+            jb2[k - k0] = (uint8_t)mb.second;
         }
         __syncthreads();
         const int j = threadIdx.x;
         if (j < n_mag) {
             int32_t pos = cur[j];
             for (int32_t k = k0; k < k1; ++k) {
-                if (jb[k - k0] == j) {
+                if (jb[k - k0] == j || jb2[k - k0] == j) {
                     dst[pos] = ok ? t[k] - t0 : 0.0;
                     ++pos;
                 }
@@ -225,7 +250,7 @@ bool search_variant_exists(int precision, int n_phase, int tq)
     return find_variant(precision, 0, n_phase, tq, 0) != nullptr;
 }
 
-size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_n)
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count)
 {
     const SearchVariant *v = find_variant(precision, 0, n_phase, tq, 0);
     const size_t regions = (size_t)(tq + 1) / 2;
@@ -233,7 +258,7 @@ size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max
     const size_t hist = regions * slots * kWave * sizeof(uint32_t);
     const size_t marg = regions * (size_t)n_phase * kWave * sizeof(uint32_t);
     size_t bytes = ((v && v->nph == 0) ? hist + marg : hist) * search_waves_per_block(lut_lds);
-    if (lut_lds) bytes += sizeof(double) * (size_t)(max_n + 1);
+    if (lut_lds) bytes += sizeof(double) * (size_t)(max_count + 1);
     return bytes;
 }
 
@@ -242,7 +267,7 @@ hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
     const SearchVariant *v =
         find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds);
     if (!v) return hipErrorInvalidValue;
-    const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_n);
+    const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_count);
     const int wpb = search_waves_per_block(dp.lut_lds);
     const int64_t blocks = (dp.n_units + wpb - 1) / wpb;
     const int64_t gx = blocks < kSearchGridX ? blocks : kSearchGridX;
@@ -350,7 +375,7 @@ __global__ __launch_bounds__(64) void k_debug_counts(
     const double invp = dp.inv_p[p], ha = dp.half_pd[q];
     const float ha32 = dp.half_pd32[q];
     const double half_bin = split_shift(nph);
-    const int64_t base = dp.off[c];
+    const int64_t base = dp.mag_overlap ? 2 * dp.off[c] : dp.off[c];
     const int32_t *segc = dp.seg + c * (int64_t)(nmag + 1);
     for (int32_t j = 0; j < nmag; ++j) {
         for (int32_t k = segc[j]; k < segc[j + 1]; ++k) {

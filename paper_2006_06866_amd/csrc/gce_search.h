@@ -62,11 +62,11 @@ void k_search(DevPlan dp, void *out_ce_v)
     const int nslot = nph + S::kWrap;                   // LDS words per region
     // LDS: [c ln c table (LL)] then one region per wave:
     // [R][nslot][64] histogram words, then [R][nph][64] marginals (NPH == 0)
-    const size_t table_words = LL ? (size_t)2 * (dp.max_n + 1) : 0;
+    const size_t table_words = LL ? (size_t)2 * (dp.max_count + 1) : 0;
     const size_t wave_words = (size_t)R * (nslot + (S::kLdsMarg ? nph : 0)) * kWave;
     double *lut_lds = reinterpret_cast<double *>(lds);
     if (LL) {   // before any wave of the block may leave
-        for (int c = threadIdx.x; c <= dp.max_n; c += kWave * WPB) lut_lds[c] = dp.lut[c];
+        for (int c = threadIdx.x; c <= dp.max_count; c += kWave * WPB) lut_lds[c] = dp.lut[c];
         __syncthreads();
     }
     // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
@@ -78,8 +78,10 @@ void k_search(DevPlan dp, void *out_ce_v)
     const int32_t g = (int32_t)(rem / dp.n_ptiles);
     const int64_t tile = rem - (int64_t)g * dp.n_ptiles;
     const int32_t c = dp.order[rank];
-    const int64_t base = dp.off[c];
-    const int32_t n = (int32_t)(dp.off[c + 1] - base);
+    // the curve's sorted epochs start at off[c], or 2 off[c] with overlapping
+    // magnitude bins (mag_overlap is 0 or 1; a shift keeps this scalar, where
+    // a select cost 18 VGPRs in the 10-bin, 4-trial kernel)
+    const int64_t base = dp.off[c] << dp.mag_overlap;
     const int64_t p = tile * kWave + lane;
     const bool p_ok = p < dp.n_p;
     const int32_t q0 = g * TQ;
@@ -204,7 +206,8 @@ void k_search(DevPlan dp, void *out_ce_v)
     // One pass over the phase bins.  With 50%-overlapping bins, bin b
     // spans disjoint bins b and b + 1 (mod n): its count is the sum of the
     // two words (packed halves cannot overflow: together they hold at most
-    // the curve's N epochs).  Bin 0's word (wrap slot merged) is kept in a
+    // the segment's entries, or twice that for a single phase bin, within
+    // the plan's count bound).  Bin 0's word (wrap slot merged) is kept in a
     // register for the last bin, so every cell is cleared as soon as it is
     // read.
     // With the table in LDS (and NPH > 0) cells are never cleared.  They hold
@@ -361,8 +364,11 @@ void k_search(DevPlan dp, void *out_ce_v)
         }
     }
 
-    // probabilities are counts / N, or counts / (2N) with overlapping bins
-    const double nd = OVL ? 2.0 * (double)n : (double)n;
+    // probabilities are counts over the histogram total: the curve's
+    // entries (N, or up to 2N with overlapping magnitude bins), twice that
+    // with overlapping phase bins
+    const double entries = (double)segc[dp.n_mag];
+    const double nd = OVL ? 2.0 * entries : entries;
     double best_h = NAN;
     int64_t best_f = -1;
     double hv[TQ];

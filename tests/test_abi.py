@@ -103,3 +103,28 @@ def test_valid_shape_needs_a_gfx950_device():
     with pytest.raises(gce.GceError) as ei:
         gce.Plan(np.array([0, 5, 9]), 10, 2, 10, 5, device="cuda:0")
     assert ei.value.status == -5
+
+
+def test_overlap_count_limits_rejected_on_host():
+    """Overlapping bins count an epoch more than once; the 16-bit counts
+    bound the longest curve (halved with overlapping magnitude bins, again
+    for one overlapping phase bin, and at 8191 counts with the table in LDS)."""
+    _ensure_built()
+    cases = [
+        (dict(mag_overlap=True), 10, 32768),
+        (dict(mag_overlap=True, phase_overlap=True), 1, 16384),
+        (dict(phase_overlap=True), 1, 32768),
+        (dict(mag_overlap=True, table_placement=gce.TABLE_LDS), 10, 4096),
+    ]
+    for kw, n_phase, n in cases:
+        with pytest.raises(gce.GceError) as ei:
+            gce.Plan(np.array([0, n]), 10, 2, n_phase, 5, device="cuda:0", **kw)
+        assert ei.value.status == -6, (kw, n_phase, n)
+    L = gce.lib()
+    off = np.array([0, 5], dtype=np.int64)
+    h = ctypes.c_void_p()
+    for bad in (gce._Opts(0, 0, 0, 0, 2), gce._Opts(0, 0, 0, 0, -1)):
+        rc = L.gce_plan_create(ctypes.byref(h),
+                               off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, 10,
+                               2, 10, 5, ctypes.byref(bad), 0)
+        assert rc == -1

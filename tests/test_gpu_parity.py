@@ -20,24 +20,27 @@ pytestmark = pytest.mark.gpu
 
 
 def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0,
-                 phase_overlap=False, table_placement=0):
+                 phase_overlap=False, table_placement=0, mag_overlap=False):
     say(f"[parity] {label}: curves={w.n_curves} N={w.lengths.tolist()[:8]} "
         f"n_p={w.periods.size} n_pd={w.pdots.size} bins={w.n_phase}x{w.n_mag} "
-        f"tq={trials_per_lane} overlap={phase_overlap} table={table_placement}")
+        f"tq={trials_per_lane} overlap={phase_overlap}/{mag_overlap} table={table_placement}")
     plan, dev, cube, best = run_gpu(w, trials_per_lane=trials_per_lane,
                                     phase_overlap=phase_overlap,
-                                    table_placement=table_placement)
+                                    table_placement=table_placement,
+                                    mag_overlap=mag_overlap)
     if table_placement:
         assert plan.info()["table_in_lds"] == int(table_placement == gce.TABLE_LDS)
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
-                                 w.n_phase, w.n_mag, phase_overlap=phase_overlap)
+                                 w.n_phase, w.n_mag, phase_overlap=phase_overlap,
+                                 mag_overlap=mag_overlap)
     gc = cube.cpu().numpy()
     bf = gce.best_fields(best)
-    assert_cube_close(gc, oc, w, label)
-    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, label)
+    cm = 2 if mag_overlap else 1
+    assert_cube_close(gc, oc, w, label, count_mult=cm)
+    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, label, count_mult=cm)
     assert np.array_equal(bf["period_index"], bf["flat_index"] % w.periods.size)
     assert np.array_equal(bf["pdot_index"], bf["flat_index"] // w.periods.size)
-    _check_statistics(bf, oc, w, label)
+    _check_statistics(bf, oc, w, label, count_mult=cm)
     rng = np.random.default_rng(seed)
     n_tr = w.periods.size * w.pdots.size
     ci = rng.integers(0, w.n_curves, counts_sample)
@@ -48,14 +51,14 @@ def _full_parity(w, label, trials_per_lane=0, counts_sample=400, seed=0,
     plan.close()
 
 
-def _check_statistics(bf, oc, w, label):
+def _check_statistics(bf, oc, w, label, count_mult=1):
     """Eq. (5) inputs against the oracle's two-pass moments of its own cube:
     every CE value is within tol of the oracle's, so the mean and the
     population std are too (both are 1-Lipschitz in the max norm), plus
     summation rounding."""
     om, osd, orho = oracle.curve_statistics(oc)
     tol = ce_tolerance(np.abs(oc).reshape(w.n_curves, -1).max(axis=1), w.n_phase,
-                       w.n_mag, w.lengths)
+                       w.n_mag, count_mult * w.lengths)
     n = oc[0].size
     rnd = 4 * n * 2.0 ** -53 * np.abs(om) + 1e-15
     assert np.all(np.abs(bf["ce_mean"] - om) <= tol + rnd), label
@@ -303,7 +306,7 @@ def test_batches_merge_to_single_search(axis):
 
 @pytest.mark.parametrize("n_phase,n_mag,tq", [
     (10, 5, 0), (10, 5, 8), (50, 10, 0), (15, 5, 4), (7, 3, 2), (2, 2, 0), (1, 1, 0),
-    (20, 10, 8),
+    (20, 10, 8), (1, 5, 0), (1, 5, 2),
 ])
 def test_overlapping_phase_bins(n_phase, n_mag, tq):
     """50%-overlapping phase bins (Sec. 2.3): counts bit-exact and CE within
@@ -312,6 +315,60 @@ def test_overlapping_phase_bins(n_phase, n_mag, tq):
     w = synth.random_curves(80 + n_phase + tq, EDGE_LENGTHS, n_freq=130, n_pdots=6,
                             n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
     _full_parity(w, f"overlap nph={n_phase}", trials_per_lane=tq, phase_overlap=True)
+
+
+@pytest.mark.parametrize("n_phase,n_mag,tq,phase_overlap,placement", [
+    (10, 5, 0, False, 0), (10, 5, 8, True, 0), (50, 10, 0, True, 0), (7, 3, 2, False, 0),
+    (20, 10, 8, False, 0), (33, 255, 2, False, 0), (2, 2, 0, True, 0), (1, 5, 0, True, 0),
+    (1, 5, 0, False, 0), (10, 1, 4, False, 0), (128, 5, 1, True, 0),
+    (10, 5, 8, False, gce.TABLE_LDS), (50, 10, 2, True, gce.TABLE_LDS),
+    (1, 5, 0, True, gce.TABLE_LDS), (10, 5, 2, False, gce.TABLE_GLOBAL),
+])
+def test_overlapping_magnitude_bins(n_phase, n_mag, tq, phase_overlap, placement):
+    """50%-overlapping magnitude bins (Sec. 2.3), alone and with
+    overlapping phase bins: an epoch is counted in each magnitude bin whose
+    span holds it, probabilities are counts over the histogram total.
+    Counts bit-exact, CE within tolerance, minima and statistics."""
+    w = synth.random_curves(140 + n_phase + n_mag + tq, EDGE_LENGTHS, n_freq=130,
+                            n_pdots=6, n_phase=n_phase, n_mag=n_mag, pdot_scale=5e-9)
+    _full_parity(w, f"mag overlap nph={n_phase} nmag={n_mag}", trials_per_lane=tq,
+                 phase_overlap=phase_overlap, table_placement=placement, mag_overlap=True)
+
+
+@pytest.mark.parametrize("precision", [gce.PRECISION_FP64, gce.PRECISION_SPLIT_FP32])
+def test_magnitude_overlap_largest_curves(precision):
+    """Curves at the magnitude-overlap limit, 32,767 epochs, with the table in
+    global memory (the counts reach 2N = 65,534), and 3,000 with it in LDS
+    (counts in units of 8 reach 48,000; the table then fills most of the
+    LDS, so one trial per lane).  The
+    FP64 path against the oracle on sampled trials (counts bit-exact, CE in
+    tolerance); the split path's CE against Eq. (4) of its own histograms,
+    which must hold each curve's entries."""
+    for n, placement, tq in ((32767, gce.TABLE_GLOBAL, 0), (3000, gce.TABLE_LDS, 1)):
+        w = synth.random_curves(150 + n % 7, [n, 700], n_freq=70, n_pdots=3,
+                                n_phase=10, n_mag=5, pdot_scale=5e-9)
+        plan, dev, cube, best = run_gpu(w, precision=precision, table_placement=placement,
+                                        trials_per_lane=tq, mag_overlap=True)
+        say(f"[mag overlap limit] N={n} table={placement} prec={precision}")
+        rng = np.random.default_rng(n)
+        ids = rng.integers(0, w.periods.size * w.pdots.size, 40)
+        for c in range(2):
+            g = cube[c].reshape(-1).cpu().numpy()[ids].astype(np.float64)
+            if precision == gce.PRECISION_FP64:
+                h = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                                  np.full(ids.size, c), ids, mag_overlap=True)
+                tol = ce_tolerance(h, 10, 5, 2 * w.lengths[c])
+                assert np.all(np.abs(g - h) <= tol), (n, c)
+                check_counts_exact(plan, dev, w, np.full(8, c), ids[:8], f"N={n} c={c}")
+            else:
+                cnt = plan.debug_counts(*dev, np.full(ids.size, c), ids)
+                cnt = cnt.cpu().numpy().astype(np.uint32)
+                _, a = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                                     [c], ids[:1], want_counts=True, mag_overlap=True)
+                assert np.all(cnt.sum(axis=(1, 2)) == a.sum())   # the curve's entries
+                h_own = np.array([oracle.entropy(x) for x in cnt])
+                assert np.all(np.abs(g - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12), (n, c)
+        plan.close()
 
 
 def test_overlap_rejects_nothing_and_differs_from_disjoint():
@@ -381,8 +438,9 @@ def test_chunked_search_matches_one_launch(tmp_path, overlap):
     w = synth.random_curves(120 + overlap, [64, 300, 1000], n_freq=900, n_pdots=6,
                             n_phase=20, n_mag=5, pdot_scale=5e-9)
     t, m, P, Pd = upload(w)
+    # overlap: both overlapping phase and magnitude bins
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
-                    phase_overlap=overlap)
+                    phase_overlap=overlap, mag_overlap=overlap)
     _, best = plan.execute(t, m, P, Pd)
     torch.cuda.synchronize()
     want = gce.best_fields(best)
@@ -400,14 +458,16 @@ def test_chunked_search_matches_one_launch(tmp_path, overlap):
 
     with pytest.raises(Stop):
         chunked.search_chunked(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, 256,
-                               checkpoint=ck, phase_overlap=overlap, on_range=stop_after_two)
+                               checkpoint=ck, phase_overlap=overlap, mag_overlap=overlap,
+                               on_range=stop_after_two)
     # the interrupted range ran but its callback raised before the save
     assert chunked.load_checkpoint(ck, chunked.fingerprint(
         [w.offsets, w.times, w.mags, w.periods, w.pdots], n_phase=w.n_phase,
-        n_mag=w.n_mag, precision=0, phase_overlap=overlap, chunk=256))[1] == 1
+        n_mag=w.n_mag, precision=0, phase_overlap=overlap, mag_overlap=overlap,
+        chunk=256))[1] == 1
     seen.clear()
     acc = chunked.search_chunked(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, 256,
-                                 checkpoint=ck, phase_overlap=overlap,
+                                 checkpoint=ck, phase_overlap=overlap, mag_overlap=overlap,
                                  on_range=lambda i, p0, p1, c: seen.append((p0, p1)))
     assert seen == [(256, 512), (512, 768), (768, 900)]
     got = gce.best_fields(acc)
