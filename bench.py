@@ -45,7 +45,7 @@ WORKLOADS = {
 TABLES = {"auto": 0, "global": 1, "lds": 2}
 
 
-def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
+def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n, entries_per_point=1.0):
     """Algorithmic flops per point-trial (FMA = 2), the precision's own kind.
 
     FP64: per point and trial y = fma(-Pdot/2, x^2, x) (2), y - floor(y) (1),
@@ -53,11 +53,13 @@ def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n):
     x = dt * (1/P) (1) and x^2 (1).  Split: the per-trial part in FP32, the
     same 4 flops.  Both: per trial the entropy sums, n_phase * (n_mag + 1)
     additions, a subtraction and a division, spread over the curve's points.
+    With overlapping magnitude bins the per-point part is done once per
+    histogram entry (entries_per_point per epoch).
     """
-    return 4.0 + 2.0 / n_pd + (n_phase * (n_mag + 1) + 2) / mean_n
+    return (4.0 + 2.0 / n_pd) * entries_per_point + (n_phase * (n_mag + 1) + 2) / mean_n
 
 
-def valu_instr_per_point_trial(precision, tq, w):
+def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
     """VALU issue slots the kernel's design takes per point-trial, in units
     of one wave64 instruction on one SIMD (4 cycles; measured on MI355X:
     v_fma_f64, v_add_f64, v_fract_f64, v_cvt_i32_f64, v_fract_f32 and
@@ -75,9 +77,12 @@ def valu_instr_per_point_trial(precision, tq, w):
     adds, plus the neighbour add with overlapping bins.  A wave holds
     ceil(tq / 2) words per bin and folds n_mag segments per work unit, so
     over the workload this adds n_mag * n_phase * ceil(tq / 2) * k per wave
-    against sum(N) * tq point-trials per lane."""
+    against sum(N) * tq point-trials per lane.
+
+    With overlapping magnitude bins an epoch is folded once per magnitude
+    bin that holds it: the per-point part scales by the entries per epoch."""
     import numpy as np
-    point = 4.0 + 2.0 / tq if precision == 0 else 3.0 + 6.0 / tq
+    point = (4.0 + 2.0 / tq if precision == 0 else 3.0 + 6.0 / tq) * entries_per_point
     k = 5.0 + (1.0 if w.phase_overlap else 0.0)
     words = (tq + 1) // 2
     lengths = np.asarray(w.lengths, dtype=np.float64)
@@ -103,13 +108,15 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
     t0 = time.perf_counter()
     oracle.search(probe.times, probe.mags, probe.offsets, probe.periods[:probe_p],
                   probe.pdots, probe.n_phase, probe.n_mag, n_threads=threads,
-                  want_cube=False, phase_overlap=w.phase_overlap)
+                  want_cube=False, phase_overlap=w.phase_overlap,
+                  mag_overlap=w.mag_overlap)
     per_period = (time.perf_counter() - t0) / probe_p
     sliced = per_period * n_p > 0.5 * budget_s
     if sliced:
         n_p = max(probe_p, int(0.25 * budget_s / per_period))
         w = synth.Workload(w.name, w.times, w.mags, w.offsets, w.periods[:n_p], w.pdots,
-                           w.n_phase, w.n_mag, phase_overlap=w.phase_overlap)
+                           w.n_phase, w.n_mag, phase_overlap=w.phase_overlap,
+                           mag_overlap=w.mag_overlap)
     done, spent, pt = 0, 0.0, 0
     max_err, best_agree, best_checked = 0.0, 0, 0
     per_curve = None
@@ -124,7 +131,8 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
         oc, obf, obc = oracle.search(sub.times, sub.mags, sub.offsets, sub.periods,
                                      sub.pdots, sub.n_phase, sub.n_mag, n_threads=threads,
                                      want_cube=g is not None,
-                                     phase_overlap=w.phase_overlap)
+                                     phase_overlap=w.phase_overlap,
+                                     mag_overlap=w.mag_overlap)
         spent += time.perf_counter() - t0
         pt += sub.point_trials
         per_curve = spent / (done + k)
@@ -151,7 +159,8 @@ def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube
     from a separate eager pass with events."""
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
                     precision=precision, trials_per_lane=tq,
-                    phase_overlap=w.phase_overlap, table_placement=table, device=dev)
+                    phase_overlap=w.phase_overlap, table_placement=table,
+                    mag_overlap=w.mag_overlap, device=dev)
     return _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph)
 
 
@@ -210,10 +219,13 @@ def search_source_sha256(texts=None):
     return h.hexdigest()
 
 
-def measured_traffic(config, precision):
+def measured_traffic(config, precision, as_recorded=True):
     """HBM bytes per search launch from the committed rocprofv3 counter
     summary, or None when the kernel source has changed since it was taken
-    or the workload differs."""
+    or the run differs from the recorded one (as_recorded: the whole
+    workload, default options)."""
+    if not as_recorded:
+        return None
     path = os.path.join(ROOT, "profiles", f"k_search_c{config}_traffic.json")
     try:
         with open(path) as f:
@@ -227,16 +239,21 @@ def measured_traffic(config, precision):
     return rec.get("per_launch_bytes", {}).get(key)
 
 
-def roofline(precision, w, kernel_s, config, tq):
+def roofline(precision, w, kernel_s, config, tq, entries_per_point=1.0, as_recorded=True):
+    """entries_per_point: histogram entries per epoch (above 1 only with
+    overlapping magnitude bins, where an epoch is folded once per bin that
+    holds it)."""
     pt = w.point_trials
     mean_n = float(w.lengths.mean())
-    fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag, mean_n)
+    fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag,
+                                mean_n, entries_per_point)
     achieved = fpp * pt / kernel_s / 1e12
     peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
-    instr = valu_instr_per_point_trial(precision, tq, w)
+    instr = valu_instr_per_point_trial(precision, tq, w, entries_per_point)
     return {
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-        "frac": achieved / peak, "traffic": measured_traffic(config, precision),
+        "frac": achieved / peak,
+        "traffic": measured_traffic(config, precision, as_recorded),
         "kernel": "k_search<%s>" % ("fp64" if precision == 0 else "split"),
         "kernel_ms": kernel_s * 1e3, "flops_per_point_trial": fpp,
         "valu_instr_per_point_trial": instr,
@@ -304,6 +321,8 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split leg")
     ap.add_argument("--table", choices=["auto", "global", "lds"], default="auto",
                     help="where the search kernel reads its c ln c table")
+    ap.add_argument("--mag-overlap", action="store_true",
+                    help="50%%-overlapping magnitude bins in every leg")
     ap.add_argument("--curves", type=int, default=0,
                     help="profiling aid: only the first CURVES curves of the workload")
     ap.add_argument("--graph", action="store_true",
@@ -357,6 +376,8 @@ def main():
     w = synth.make_config(args.config)
     if 0 < args.curves < w.n_curves:
         w = w.subset(range(args.curves))
+    if args.mag_overlap:
+        w.mag_overlap = True
     log(f"workload {WORKLOADS[args.config]}: {w.point_trials:.3g} point-trials")
     inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
     pt = w.point_trials
@@ -367,6 +388,16 @@ def main():
         gce, torch, np, w, dev, inputs, 0, args.trials_per_lane, args.steps,
         args.warmup, cube_on, args.graph, TABLES[args.table])
     log(f"fp64: {el64 / args.steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
+    # histogram entries per epoch: the total of one trial's histogram per
+    # curve (it does not depend on the trial)
+    entries = 1.0
+    if w.mag_overlap:
+        tot = plan64.debug_counts(*inputs, np.arange(w.n_curves),
+                                  np.zeros(w.n_curves, dtype=np.int64)).sum().item()
+        entries = float(tot) / float(w.offsets[-1]) / (2.0 if w.phase_overlap else 1.0)
+    # the committed traffic record is of the whole workload with default options
+    as_recorded = (args.curves <= 0 and not args.no_cube and not args.mag_overlap
+                   and args.table == "auto" and args.trials_per_lane == 0)
     value = pt * args.steps / el64
     bf64 = gce.best_fields(best64)
 
@@ -392,8 +423,11 @@ def main():
             "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
             "table_in_lds": bool(plan64.info()["table_in_lds"]),
             "timing": "hip-graph replay" if args.graph else "eager launches",
+            "mag_overlap": bool(w.mag_overlap),
+            "entries_per_epoch": entries,
         },
-        "roofline": roofline(0, w, k64, args.config, plan64.info()["trials_per_lane"]),
+        "roofline": roofline(0, w, k64, args.config, plan64.info()["trials_per_lane"],
+                             entries, as_recorded),
     }
     if "p_true" in w.truth:
         # injections off the grid (Sec. 3.1 criterion), and the same search
@@ -404,7 +438,8 @@ def main():
         out["recovery_fp64"] = {"all": recovery.summary(bf64, w.periods, ptrue),
                                 "p0_le_10min": recovery.summary(bf64, w.periods, ptrue, short)}
         plan0 = gce.Plan(w.offsets, w.periods.size, 1, w.n_phase, w.n_mag,
-                         phase_overlap=w.phase_overlap, device=dev)
+                         phase_overlap=w.phase_overlap, mag_overlap=w.mag_overlap,
+                         device=dev)
         _, b0 = plan0.execute(inputs[0], inputs[1], inputs[2],
                               torch.zeros(1, dtype=torch.float64, device=dev))
         torch.cuda.synchronize()
@@ -435,7 +470,8 @@ def main():
             "speedup_vs_fp64": el64 / el32,
             "trials_per_lane": plan32.info()["trials_per_lane"],
             "table_in_lds": bool(plan32.info()["table_in_lds"]),
-            "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"]),
+            "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"],
+                                 entries, as_recorded),
             "best_equal_strict": f"{strict}/{w.n_curves}",
         }
         if cube_on:

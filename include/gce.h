@@ -121,7 +121,9 @@ typedef struct {
     int32_t phase_overlap;   /* nonzero: 50%-overlapping phase bins (Sec. 2.3):
                                 bin k spans phases [k, k + 2) / n_phase, wrapping,
                                 so every epoch counts in two bins and the
-                                probabilities of Eq. (4) are counts / (2N) */
+                                probabilities of Eq. (4) are counts over the
+                                histogram total (2N without magnitude
+                                overlap) */
     int32_t table_placement; /* c ln c table read by the entropy sums:
                                 0 = automatic, 1 = global memory, 2 = a copy in
                                 each wave's LDS (pays off when there are many

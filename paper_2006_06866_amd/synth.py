@@ -45,6 +45,7 @@ class Workload:
     n_mag: int
     truth: Dict[str, np.ndarray] = field(default_factory=dict)
     phase_overlap: bool = False     # 50%-overlapping phase bins (Sec. 2.3)
+    mag_overlap: bool = False       # 50%-overlapping magnitude bins (Sec. 2.3)
 
     @property
     def n_curves(self) -> int:
@@ -76,7 +77,8 @@ class Workload:
         truth = {k: v[curves] for k, v in self.truth.items()}
         return Workload(self.name + "[subset]", np.concatenate(ts),
                         np.concatenate(ms), off, self.periods, self.pdots,
-                        self.n_phase, self.n_mag, truth, self.phase_overlap)
+                        self.n_phase, self.n_mag, truth, self.phase_overlap,
+                        self.mag_overlap)
 
 
 # ----------------------------------------------------------------------------
