@@ -280,7 +280,8 @@ int gce_plan_destroy(gce_plan_t plan);
  * error of the calling thread's last failing call. */
 const char *gce_status_string(int status);
 
-/* Library version string. */
+/* Library version string ("gce-mi355x 0.2.0 (gfx950)"; 0.2.0 appended
+ * mag_overlap to gce_opts and to gce_autotune's arguments). */
 const char *gce_version(void);
 
 #ifdef __cplusplus

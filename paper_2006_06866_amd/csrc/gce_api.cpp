@@ -276,7 +276,7 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 
 extern "C" {
 
-const char *gce_version(void) { return "gce-mi355x 0.1.0 (gfx950)"; }
+const char *gce_version(void) { return "gce-mi355x 0.2.0 (gfx950)"; }
 
 const char *gce_status_string(int status)
 {

@@ -128,3 +128,34 @@ def test_overlap_count_limits_rejected_on_host():
                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, 10,
                                2, 10, 5, ctypes.byref(bad), 0)
         assert rc == -1
+
+
+def _write_inputs(d, w):
+    w.times.astype("<f8").tofile(os.path.join(d, "times.f64"))
+    w.mags.astype("<f8").tofile(os.path.join(d, "mags.f64"))
+    np.asarray(w.offsets, dtype="<i8").tofile(os.path.join(d, "offsets.i64"))
+    w.periods.astype("<f8").tofile(os.path.join(d, "periods.f64"))
+    w.pdots.astype("<f8").tofile(os.path.join(d, "pdots.f64"))
+
+
+def test_file_search_program_rejects_bad_use_on_host(tmp_path):
+    """The command-line program over raw files: usage, I/O and shape errors
+    are reported before any GPU work."""
+    import subprocess
+    from paper_2006_06866_amd import synth
+    if not os.path.exists(gbuild.FILE_SEARCH):
+        gbuild.build()
+    exe = gbuild.FILE_SEARCH
+    assert subprocess.run([exe], capture_output=True).returncode == 2
+    assert subprocess.run([exe, str(tmp_path), "10", "5", "--bogus"],
+                          capture_output=True).returncode == 2
+    r = subprocess.run([exe, str(tmp_path), "10", "5"], capture_output=True, text=True)
+    assert r.returncode == 1 and "cannot open" in r.stderr
+    w = synth.random_curves(3, [20, 30], n_freq=8, n_pdots=2)
+    _write_inputs(str(tmp_path), w)
+    r = subprocess.run([exe, str(tmp_path), "129", "5"], capture_output=True, text=True)
+    assert r.returncode == 1 and "invalid argument" in r.stderr
+    with open(os.path.join(str(tmp_path), "mags.f64"), "ab") as f:
+        f.write(b"\0" * 8)   # one magnitude too many
+    r = subprocess.run([exe, str(tmp_path), "10", "5"], capture_output=True, text=True)
+    assert r.returncode == 1 and "inconsistent" in r.stderr

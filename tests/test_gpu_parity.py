@@ -558,3 +558,37 @@ def test_tilings_agree():
                 if f0 != f1:
                     q, p = divmod(f1, w.periods.size)
                     assert ref[0][c, q, p] <= ref[1]["ce_min"][c] + 2 * tol[c, 0, 0], (tq, placement, c)
+
+
+@pytest.mark.parametrize("flags,phase_overlap,mag_overlap", [
+    ([], False, False), (["--phase-overlap", "--mag-overlap"], True, True),
+    (["--mag-overlap", "--table", "lds", "--trials-per-lane", "2"], False, True),
+])
+def test_file_search_program_matches_oracle(tmp_path, flags, phase_overlap, mag_overlap):
+    """The C-ABI used from a native program (no Python in the search): inputs
+    from raw files, results written to files, compared with the oracle."""
+    import os
+    import subprocess
+    from paper_2006_06866_amd import build as gbuild
+    w = synth.random_curves(170 + len(flags), EDGE_LENGTHS, n_freq=110, n_pdots=5,
+                            n_phase=15, n_mag=5, pdot_scale=5e-9)
+    d = str(tmp_path)
+    w.times.astype("<f8").tofile(os.path.join(d, "times.f64"))
+    w.mags.astype("<f8").tofile(os.path.join(d, "mags.f64"))
+    np.asarray(w.offsets, dtype="<i8").tofile(os.path.join(d, "offsets.i64"))
+    w.periods.astype("<f8").tofile(os.path.join(d, "periods.f64"))
+    w.pdots.astype("<f8").tofile(os.path.join(d, "pdots.f64"))
+    say(f"[file search] flags={flags}")
+    r = subprocess.run([gbuild.FILE_SEARCH, d, "15", "5", "--cube", *flags],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    say(r.stdout.strip())
+    cube = np.fromfile(os.path.join(d, "cube.f64"), dtype="<f8").reshape(
+        w.n_curves, w.pdots.size, w.periods.size)
+    bf = gce.best_fields(np.fromfile(os.path.join(d, "best.bin"), dtype=np.uint8))
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 15, 5,
+                                 phase_overlap=phase_overlap, mag_overlap=mag_overlap)
+    cm = 2 if mag_overlap else 1
+    assert_cube_close(cube, oc, w, "file search", count_mult=cm)
+    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "file search",
+                      count_mult=cm)
