@@ -26,6 +26,9 @@
 #ifndef GCE_FLUSH_ACC
 #define GCE_FLUSH_ACC 4         // partial entropy sums per trial (trials_per_lane <= 2)
 #endif
+#ifndef GCE_FLUSH_WORDS
+#define GCE_FLUSH_WORDS 8       // histogram words per scheduling group of the flush
+#endif
 #ifndef GCE_SCALAR_EPOCHS
 #define GCE_SCALAR_EPOCHS 1     // read epoch offsets with scalar loads
 #endif

@@ -34,9 +34,13 @@ struct SearchShape {
     static constexpr int kRegions = (TQ + 1) / 2;
     static constexpr bool kLdsMarg = (NPH == 0);
     static constexpr int kWrap = (PREC == kPrecSplit) ? 1 : 0;   // extra slot
-    // phase bins per scheduling group of the segment flush: ~8 words,
-    // i.e. ~16 table loads, in flight at a time
-    static constexpr int kFlushGroup = kRegions >= 8 ? 1 : 8 / kRegions;
+    // phase bins per scheduling group of the segment flush: about
+    // GCE_FLUSH_WORDS words, i.e. twice that many table loads, in flight
+    static constexpr int kFlushGroup =
+        kRegions >= GCE_FLUSH_WORDS ? 1 : GCE_FLUSH_WORDS / kRegions;
+    // the same for the cumulative flush (table in LDS): 12 bins with one
+    // trial pair (24 table loads), else as above (more cost registers)
+    static constexpr int kCumGroup = kRegions == 1 ? 12 : kFlushGroup;
 };
 
 // LL = 1: the c ln c table is copied into LDS, shared by the block's
@@ -227,20 +231,48 @@ void k_search(DevPlan dp, void *out_ce_v)
     };
     auto flush_segment = [&]() {
         if constexpr (kCum) {
-            uint32_t w0[R], wc[R];
+            // groups of G bins in three phases kept apart by compiler
+            // barriers: all cell reads, then all table loads, then the
+            // adds, so a group's table loads are in flight together (the
+            // compiler's own schedule kept 3 or 4; 2.5% faster on 50 x 10
+            // overlapping bins at N = 500)
+            constexpr int G = S::kCumGroup;
+            uint32_t w0[R], cur[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) wc[r] = w0[r] = seg_word(r, 0);
+            for (int r = 0; r < R; ++r) cur[r] = w0[r] = seg_word(r, 0);
 #pragma unroll
-            for (int b = 0; b < NPH; ++b) {
+            for (int b0 = 0; b0 < NPH; b0 += G) {
+                uint32_t wv[G + 1][R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint32_t wn = (b + 1 < NPH) ? seg_word(r, b + 1) : w0[r];
-                    add_lut(r, OVL ? wc[r] + wn : wc[r], b % KA);
-                    wc[r] = wn;
-                }
-                // bound the table loads in flight (register pressure): no
-                // memory access may move across this point
-                if ((b + 1) % S::kFlushGroup == 0) asm volatile("" ::: "memory");
+                for (int r = 0; r < R; ++r) wv[0][r] = cur[r];
+#pragma unroll
+                for (int i = 1; i <= G; ++i)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        wv[i][r] = (b0 + i < NPH) ? seg_word(r, b0 + i)
+                                                  : (b0 + i == NPH ? w0[r] : 0u);
+                asm volatile("" ::: "memory");
+                double lo[G][R], hi[G][R];
+#pragma unroll
+                for (int i = 0; i < G; ++i)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (b0 + i >= NPH) continue;
+                        const uint32_t w = OVL ? wv[i][r] + wv[i + 1][r] : wv[i][r];
+                        lo[i][r] = lut_lo(w);
+                        hi[i][r] = (2 * r + 1 < TQ) ? lut_hi(w) : 0.0;
+                    }
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int i = 0; i < G; ++i)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (b0 + i >= NPH) continue;
+                        s1[(b0 + i) % KA][2 * r] += lo[i][r];
+                        if (2 * r + 1 < TQ) s1[(b0 + i) % KA][2 * r + 1] += hi[i][r];
+                    }
+#pragma unroll
+                for (int r = 0; r < R; ++r) cur[r] = wv[G][r];
             }
             return;
         }
