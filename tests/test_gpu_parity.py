@@ -592,3 +592,47 @@ def test_file_search_program_matches_oracle(tmp_path, flags, phase_overlap, mag_
     assert_cube_close(cube, oc, w, "file search", count_mult=cm)
     assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "file search",
                       count_mult=cm)
+
+
+def _aligned_curve_workload(n, n_phase, n_mag, seed):
+    """A curve of n epochs at t = k / 8 d with two magnitude levels, plus a
+    short noisy curve.  At P = 1/8 d and Pdot = 0 every epoch of the first
+    curve folds to phase 0, so one phase bin holds all n epochs: the largest
+    counts the 16-bit cells and the marginals can hold."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(n, dtype=np.float64)
+    t0 = k / 8.0
+    m0 = (np.arange(n) % 2).astype(np.float64)
+    t1 = np.sort(rng.uniform(0.0, 500.0, 37))
+    m1 = rng.normal(size=37)
+    periods = np.concatenate([[0.125], rng.uniform(0.05, 0.3, 40)])
+    pdots = np.array([0.0, 3e-9])
+    off = np.array([0, n, n + 37], dtype=np.int64)
+    return synth.Workload("aligned", np.concatenate([t0, t1]), np.concatenate([m0, m1]),
+                          off, periods, pdots, n_phase, n_mag)
+
+
+@pytest.mark.parametrize("n,placement,tq", [
+    (65535, gce.TABLE_GLOBAL, 0), (65535, gce.TABLE_GLOBAL, 8), (7000, gce.TABLE_LDS, 1),
+])
+def test_longest_curves_fill_the_counters(n, placement, tq):
+    """Curves at the epoch limit (65,535; with the table in LDS, where counts
+    are kept in units of 8, the longest that fits the LDS): one trial puts
+    every epoch in one phase bin.  Counts bit-exact, CE within tolerance,
+    the aligned trial's CE equal to the magnitude entropy."""
+    w = _aligned_curve_workload(n, 10, 2, n)
+    say(f"[longest] N={n} table={placement} tq={tq}")
+    plan, dev, cube, best = run_gpu(w, trials_per_lane=tq, table_placement=placement)
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 2)
+    gc = cube.cpu().numpy()
+    assert_cube_close(gc, oc, w, f"N={n}")
+    # phase bin 0 holds everything at (P = 1/8, Pdot = 0): H = H(magnitude)
+    half = n // 2
+    p1, p0 = half / n, (n - half) / n
+    h_mag = -(p0 * math.log(p0) + p1 * math.log(p1))
+    assert abs(gc[0, 0, 0] - h_mag) <= 1e-12
+    ids = np.array([0, 1, 5, w.periods.size, w.periods.size + 7])
+    check_counts_exact(plan, dev, w, np.zeros(ids.size, dtype=np.int64), ids, f"N={n}")
+    cnt = plan.debug_counts(*dev, np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64))
+    assert int(cnt[0, :, 0].sum().item()) == n
+    plan.close()
