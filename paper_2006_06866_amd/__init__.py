@@ -219,8 +219,9 @@ class Plan:
                 raise ValueError("out_ce has the wrong dtype, size or device")
         if out_best is None:
             out_best = self.new_best()
-        elif out_best.numel() != self.n_curves * BEST_WORDS or out_best.device != self.device:
-            raise ValueError("out_best has the wrong size or device")
+        elif (out_best.numel() != self.n_curves * BEST_WORDS or out_best.device != self.device
+              or out_best.element_size() != 8 or not out_best.is_contiguous()):
+            raise ValueError("out_best has the wrong size, element size, layout or device")
         _check(lib().gce_plan_execute(self._h, _ptr(times), _ptr(mags), _ptr(periods),
                                       _ptr(pdots), _ptr(out_ce), _ptr(out_best),
                                       _stream_handle(stream, self.device)))
