@@ -636,3 +636,47 @@ def test_longest_curves_fill_the_counters(n, placement, tq):
     cnt = plan.debug_counts(*dev, np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64))
     assert int(cnt[0, :, 0].sum().item()) == n
     plan.close()
+
+
+def test_random_shapes_match_oracle():
+    """Seeded random shapes across every option at once: phase and magnitude
+    bin counts, trials per lane, table placement, both overlap kinds, ragged
+    lengths and grid sizes that are not multiples of the tile.  Counts
+    bit-exact on sampled trials, CE within tolerance, minima valid."""
+    rng = np.random.default_rng(2006)
+    ran = 0
+    for case in range(40):
+        n_phase = int(rng.choice([1, 2, 3, 7, 10, 15, 20, 33, 50, 64, 128]))
+        n_mag = int(rng.choice([1, 2, 3, 5, 10, 17, 255]))
+        tq = int(rng.choice([0, 1, 2, 4, 8]))
+        placement = int(rng.choice([gce.TABLE_AUTO, gce.TABLE_GLOBAL, gce.TABLE_LDS]))
+        po, mo = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+        lengths = [int(x) for x in rng.integers(1, 700, int(rng.integers(1, 6)))]
+        w = synth.random_curves(1000 + case, lengths, n_freq=int(rng.integers(1, 150)),
+                                n_pdots=int(rng.integers(1, 7)), n_phase=n_phase,
+                                n_mag=n_mag, pdot_scale=5e-9)
+        label = (f"case {case}: bins {n_phase}x{n_mag} tq={tq} table={placement} "
+                 f"overlap={po}/{mo} N={lengths} grid={w.periods.size}x{w.pdots.size}")
+        try:
+            plan, dev, cube, best = run_gpu(w, trials_per_lane=tq, phase_overlap=po,
+                                            table_placement=placement, mag_overlap=mo)
+        except gce.GceError as e:
+            # an explicit tiling that does not fit (LDS, no such variant) is
+            # refused on the host; automatic choices always fit
+            assert e.status == -6 and (tq != 0 or placement == gce.TABLE_LDS), (label, e)
+            continue
+        say(f"[random] {label}")
+        oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
+                                     n_phase, n_mag, phase_overlap=po, mag_overlap=mo)
+        cm = 2 if mo else 1
+        assert_cube_close(cube.cpu().numpy(), oc, w, label, count_mult=cm)
+        bf = gce.best_fields(best)
+        assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, label,
+                          count_mult=cm)
+        n_tr = w.periods.size * w.pdots.size
+        ci = rng.integers(0, w.n_curves, 64)
+        fi = rng.integers(0, n_tr, 64)
+        check_counts_exact(plan, dev, w, ci, fi, label)
+        plan.close()
+        ran += 1
+    assert ran >= 25
