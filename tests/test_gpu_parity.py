@@ -680,3 +680,60 @@ def test_random_shapes_match_oracle():
         plan.close()
         ran += 1
     assert ran >= 25
+
+
+_TUNE_CHILD = r"""
+import json, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2006_06866_amd as gce
+from paper_2006_06866_amd import synth
+w = synth.make_config(2).subset(np.arange(48))
+dev = torch.device("cuda:0")
+t, m, P, Pd = (torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
+out = {}
+if sys.argv[2] == "tune":
+    tq, pl, ms = gce.autotune(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag,
+                              phase_overlap=True, mag_overlap=True)
+    out = {"tq": tq, "placement": pl}
+else:
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
+                    phase_overlap=True, mag_overlap=True, device=dev)
+    out = plan.info()
+    plan.close()
+print(json.dumps(out), flush=True)
+"""
+
+
+def test_tune_cache_file_persists_overlap_choices(tmp_path):
+    """gce_autotune with both overlap kinds appends its choice to the
+    GCE_TUNE_CACHE file under the overlap bits 3; a later process creating an
+    automatic plan of that shape class reads the file and uses the choice."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = str(tmp_path / "tune.txt")
+    env = dict(os.environ, GCE_TUNE_CACHE=cache)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("[tune cache] autotune child")
+    r1 = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root, "tune"], env=env,
+                        capture_output=True, text=True, timeout=300)
+    assert r1.returncode == 0, r1.stderr[-2000:]
+    chosen = json.loads(r1.stdout.strip().splitlines()[-1])
+    lines = open(cache).read().split("\n")
+    rec = [l.split() for l in lines if l.strip()]
+    assert len(rec) == 1 and rec[0][0] == "0" and rec[0][1] == "3", rec
+    assert int(rec[0][6]) == chosen["tq"]
+    assert int(rec[0][7]) == int(chosen["placement"] == gce.TABLE_LDS)
+    # a choice the heuristics would not make, for the same shape class: the
+    # plan can only take it from the file
+    planted = (1, 0) if (chosen["tq"], chosen["placement"]) != (1, gce.TABLE_GLOBAL) else (2, 0)
+    with open(cache, "w") as f:
+        f.write(" ".join(rec[0][:6] + [str(planted[0]), str(planted[1])]) + "\n")
+    say("[tune cache] plan child")
+    r2 = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root, "plan"], env=env,
+                        capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    info = json.loads(r2.stdout.strip().splitlines()[-1])
+    assert (info["trials_per_lane"], info["table_in_lds"]) == planted
