@@ -323,6 +323,10 @@ def main():
                     help="where the search kernel reads its c ln c table")
     ap.add_argument("--mag-overlap", action="store_true",
                     help="50%%-overlapping magnitude bins in every leg")
+    ap.add_argument("--chunk-periods", type=int, default=0, metavar="P",
+                    help="also run the FP64 search in period ranges of P periods with a "
+                         "checkpoint after each (the chunked driver) and report its time "
+                         "and agreement with the single launch")
     ap.add_argument("--curves", type=int, default=0,
                     help="profiling aid: only the first CURVES curves of the workload")
     ap.add_argument("--graph", action="store_true",
@@ -456,6 +460,30 @@ def main():
                 (bf64["period_index"] == w.truth["inj_p"]) &
                 (bf64["pdot_index"] == w.truth["inj_q"]) & has)),
         }
+
+    if args.chunk_periods > 0:
+        # the period-range driver with a checkpoint after every range, timed
+        # end to end (host merges and checkpoint writes included)
+        import tempfile
+        from paper_2006_06866_amd import chunked
+        with tempfile.TemporaryDirectory(prefix="gce_chunk_") as d:
+            t0 = time.perf_counter()
+            acc = chunked.search_chunked(
+                inputs[0], inputs[1], w.offsets, inputs[2], inputs[3], w.n_phase, w.n_mag,
+                args.chunk_periods, checkpoint=os.path.join(d, "ck.npz"),
+                phase_overlap=w.phase_overlap, mag_overlap=w.mag_overlap,
+                table_placement=TABLES[args.table])
+            el = time.perf_counter() - t0
+        bc = gce.best_fields(acc)
+        n_ranges = len(chunked.range_bounds(w.periods.size, args.chunk_periods))
+        out["chunked"] = {
+            "chunk_periods": args.chunk_periods, "ranges": n_ranges,
+            "ms": el * 1e3, "one_launch_ms": el64 / args.steps * 1e3,
+            "overhead": el / (el64 / args.steps) - 1.0,
+            "best_equal": f"{int(np.sum(bc['flat_index'] == bf64['flat_index']))}/{w.n_curves}",
+            "max_abs_dmean": float(np.nanmax(np.abs(bc["ce_mean"] - bf64["ce_mean"]))),
+        }
+        log(f"chunked: {n_ranges} ranges, {el * 1e3:.1f} ms")
 
     if not args.no_split:
         plan32, cube32, best32, el32, k32 = timed_leg(
