@@ -396,7 +396,6 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     const size_t o_off = take(sizeof(int64_t) * (size_t)(n_curves + 1));
     const size_t o_order = take(sizeof(int32_t) * (size_t)n_curves);
     const size_t o_lut = take(sizeof(double) * (size_t)(max_count + 1));
-    const size_t o_lut32 = take(sizeof(float) * (size_t)(max_count + 1));
     const size_t o_dt = take(sizeof(double) * (size_t)pl->total_points *
                              (o.mag_overlap ? 2 : 1));
     const size_t o_seg = take(sizeof(int32_t) * (size_t)n_curves * (size_t)(n_mag_bins + 1));
@@ -419,7 +418,6 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.off = reinterpret_cast<const int64_t *>(w + o_off);
     dp.order = reinterpret_cast<const int32_t *>(w + o_order);
     dp.lut = reinterpret_cast<const double *>(w + o_lut);
-    dp.lut32 = reinterpret_cast<const float *>(w + o_lut32);
     dp.dt_sorted = reinterpret_cast<double *>(w + o_dt);
     dp.seg = reinterpret_cast<int32_t *>(w + o_seg);
     dp.curve_ok = reinterpret_cast<int32_t *>(w + o_cok);

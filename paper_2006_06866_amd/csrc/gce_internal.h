@@ -65,7 +65,6 @@ struct DevPlan {
     const int64_t *off;       // [n_curves + 1] curve offsets
     const int32_t *order;     // [n_curves] schedule rank -> curve
     const double *lut;        // [max_count + 1] c * ln(c)
-    const float *lut32;       // [max_count + 1] c * ln(c), float
 
     // per-execution scratch
     double *dt_sorted;        // [total] t - t0, grouped by magnitude bin; curve

@@ -15,21 +15,18 @@ namespace gce {
 // ---------------------------------------------------------------------------
 // c ln c table
 // ---------------------------------------------------------------------------
-__global__ void k_lut(double *lut, float *lut32, int32_t max_count)
+__global__ void k_lut(double *lut, int32_t max_count)
 {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c > max_count) return;
-    const double v = (c == 0) ? 0.0 : (double)c * log((double)c);
-    lut[c] = v;
-    lut32[c] = (float)v;
+    lut[c] = (c == 0) ? 0.0 : (double)c * log((double)c);
 }
 
 hipError_t launch_lut(const DevPlan &dp, hipStream_t s)
 {
     const int n = dp.max_count + 1;
     hipLaunchKernelGGL(k_lut, dim3((n + 255) / 256), dim3(256), 0, s,
-                       const_cast<double *>(dp.lut),
-                       const_cast<float *>(dp.lut32), dp.max_count);
+                       const_cast<double *>(dp.lut), dp.max_count);
     return hipGetLastError();
 }
 
