@@ -143,10 +143,29 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
         done += k
     grid = (f"first {n_p} of {full_np} periods x {w.pdots.size} Pdots" if sliced
             else f"full {n_p} x {w.pdots.size} grid")
+    # the same oracle on one thread: the first curve over a slice of the
+    # periods sized to ~2 s from a short probe
+    one = w.subset(np.arange(1))
+    p1 = min(one.periods.size, 64)
+    t0 = time.perf_counter()
+    oracle.search(one.times, one.mags, one.offsets, one.periods[:p1], one.pdots,
+                  one.n_phase, one.n_mag, n_threads=1, want_cube=False,
+                  phase_overlap=w.phase_overlap, mag_overlap=w.mag_overlap)
+    per = (time.perf_counter() - t0) / p1
+    p1 = int(min(one.periods.size, max(p1, 2.0 / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.search(one.times, one.mags, one.offsets, one.periods[:p1], one.pdots,
+                  one.n_phase, one.n_mag, n_threads=1, want_cube=False,
+                  phase_overlap=w.phase_overlap, mag_overlap=w.mag_overlap)
+    t1 = time.perf_counter() - t0
+    pt1 = int(one.offsets[-1]) * p1 * one.pdots.size
     return ({"value": pt / spent, "unit": "point-trials/s", "cores": threads,
              "kind": "oracle",
              "sample": f"{done} of {w.n_curves} curves, {grid}, {pt:.3g} point-trials "
-                       f"in {spent:.1f} s"},
+                       f"in {spent:.1f} s",
+             "value_1core": pt1 / t1,
+             "sample_1core": f"curve 0, first {p1} periods x {one.pdots.size} Pdots, "
+                             f"{pt1:.3g} point-trials in {t1:.1f} s on one thread"},
             {"curves_compared": best_checked, "max_abs_dH": max_err,
              "argmin_equal": f"{best_agree}/{best_checked}"})
 
