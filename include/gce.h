@@ -126,8 +126,10 @@ typedef struct {
                                 overlap) */
     int32_t table_placement; /* c ln c table read by the entropy sums:
                                 0 = automatic, 1 = global memory, 2 = a copy in
-                                each wave's LDS (pays off when there are many
-                                histogram cells per epoch) */
+                                LDS shared by the two waves of a block (pays
+                                off when there are many histogram cells per
+                                epoch; counts at most 8191, and the table and
+                                histograms must fit 64 KiB) */
     int32_t mag_overlap;     /* nonzero: 50%-overlapping magnitude bins (Sec.
                                 2.3): bin j spans [j, j + 2) / (n_mag + 1) of
                                 the normalised magnitude u, i.e. with
@@ -136,10 +138,10 @@ typedef struct {
                                 (one bin in the first and last half-bin).  The
                                 probabilities of Eq. (4) are counts over the
                                 histogram's total count.  Curves may then hold
-                                at most 32767 epochs (4095 with the table in
-                                LDS); with phase_overlap and n_phase_bins = 1
-                                the limits halve again (GCE_EUNSUPPORTED
-                                beyond them). */
+                                at most 32767 epochs (at most 4095 with the
+                                table in LDS); with phase_overlap and
+                                n_phase_bins = 1 the limits halve again
+                                (GCE_EUNSUPPORTED beyond them). */
 } gce_opts;
 
 #define GCE_TABLE_AUTO 0
