@@ -124,3 +124,52 @@ def test_split_constant_and_invalid():
     assert np.all(gcube[0] == 0.0) and np.all(gcube[1] == 0.0)
     assert bf["flat_index"][0] == 0 and bf["flat_index"][1] == 0
     assert bf["flat_index"][2] == -1 and np.all(np.isnan(gcube[2]))
+
+
+def test_split_random_shapes_self_consistent():
+    """Seeded random shapes on the split path, every option drawn at once:
+    each sampled CE value is Eq. (4) of the split path's own histogram (to
+    float output rounding), histogram totals are the curve's entries, and the
+    bins agree with the FP64 oracle's but for a small fraction near edges."""
+    rng = np.random.default_rng(6866)
+    ran = 0
+    for case in range(24):
+        n_phase = int(rng.choice([1, 2, 7, 10, 15, 20, 33, 50, 64]))
+        n_mag = int(rng.choice([1, 2, 5, 10, 17, 255]))
+        tq = int(rng.choice([0, 1, 2, 4, 8]))
+        placement = int(rng.choice([gce.TABLE_AUTO, gce.TABLE_GLOBAL, gce.TABLE_LDS]))
+        po, mo = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+        lengths = [int(x) for x in rng.integers(1, 700, int(rng.integers(1, 6)))]
+        w = synth.random_curves(2000 + case, lengths, n_freq=int(rng.integers(1, 120)),
+                                n_pdots=int(rng.integers(1, 6)), n_phase=n_phase,
+                                n_mag=n_mag, pdot_scale=5e-9)
+        label = (f"case {case}: bins {n_phase}x{n_mag} tq={tq} table={placement} "
+                 f"overlap={po}/{mo} N={lengths}")
+        t, m, P, Pd = upload(w)
+        try:
+            plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, n_phase, n_mag,
+                            precision=gce.PRECISION_SPLIT_FP32, trials_per_lane=tq,
+                            phase_overlap=po, mag_overlap=mo, table_placement=placement)
+        except gce.GceError as e:
+            assert e.status == -6, (label, e)
+            continue
+        say(f"[split random] {label}")
+        cube, best = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+        torch.cuda.synchronize()
+        g = cube.cpu().numpy()
+        n_tr = w.periods.size * w.pdots.size
+        ci = rng.integers(0, w.n_curves, 96)
+        fi = rng.integers(0, n_tr, 96)
+        cnt = plan.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy().astype(np.uint32)
+        _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, n_phase,
+                                n_mag, ci, fi, want_counts=True, phase_overlap=po,
+                                mag_overlap=mo)
+        assert np.array_equal(cnt.sum(axis=(1, 2)), want.sum(axis=(1, 2))), label
+        h_own = np.array([oracle.entropy(c) for c in cnt])
+        q, p = np.divmod(fi, w.periods.size)
+        assert np.all(np.abs(g[ci, q, p] - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12), label
+        moved = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2
+        assert moved <= max(2.0, 1e-3 * want.sum()), (label, moved)
+        plan.close()
+        ran += 1
+    assert ran >= 15
