@@ -173,20 +173,27 @@ def test_constant_magnitudes_and_single_epoch():
     assert_cube_close(gc, oc, w, "constant")
 
 
-def test_invalid_values_mark_curves():
+@pytest.mark.parametrize("mag_overlap", [False, True])
+def test_invalid_values_mark_curves(mag_overlap):
     w = synth.random_curves(34, [40, 50, 60], n_freq=70, n_pdots=3)
     mags = w.mags.copy()
     mags[w.offsets[1] + 7] = np.nan
     w_bad = synth.Workload("bad", w.times, mags, w.offsets, w.periods, w.pdots, 10, 5)
-    plan, dev, cube, best = run_gpu(w_bad)
+    plan, dev, cube, best = run_gpu(w_bad, mag_overlap=mag_overlap)
     gc = cube.cpu().numpy()
     bf = gce.best_fields(best)
     assert bf["flat_index"].tolist()[1] == -1 and math.isnan(bf["ce_min"][1])
     assert np.all(np.isnan(gc[1]))
-    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5)
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                                 mag_overlap=mag_overlap)
     keep = [0, 2]
     sub = w.subset(keep)
-    assert_cube_close(gc[keep], oc[keep], sub, "valid curves beside a NaN curve")
+    assert_cube_close(gc[keep], oc[keep], sub, "valid curves beside a NaN curve",
+                      count_mult=2 if mag_overlap else 1)
+    if mag_overlap:
+        assert_best_valid(bf["flat_index"][keep], bf["ce_min"][keep], obf[keep], obc[keep],
+                          oc[keep], sub, "valid curves beside a NaN curve", count_mult=2)
+        return
     assert np.array_equal(bf["flat_index"][keep], obf[keep])
     # a bad period invalidates every curve
     periods = w.periods.copy()
