@@ -444,7 +444,7 @@ def main():
             "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
             "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
             "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
-            "table_in_lds": bool(plan64.info()["table_in_lds"]),
+            "table_in_lds": int(plan64.info()["table_in_lds"]),
             "timing": "hip-graph replay" if args.graph else "eager launches",
             "mag_overlap": bool(w.mag_overlap),
             "entries_per_epoch": entries,
@@ -516,7 +516,7 @@ def main():
             "ms_per_step": el32 / args.steps * 1e3,
             "speedup_vs_fp64": el64 / el32,
             "trials_per_lane": plan32.info()["trials_per_lane"],
-            "table_in_lds": bool(plan32.info()["table_in_lds"]),
+            "table_in_lds": int(plan32.info()["table_in_lds"]),
             "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"],
                                  entries, as_recorded),
             "best_equal_strict": f"{strict}/{w.n_curves}",

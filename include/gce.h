@@ -129,7 +129,9 @@ typedef struct {
                                 LDS shared by the two waves of a block (pays
                                 off when there are many histogram cells per
                                 epoch; counts at most 8191, and the table and
-                                histograms must fit 64 KiB) */
+                                histograms must fit 64 KiB).  Automatic may
+                                also search a ragged batch's shortest curves
+                                in a second launch with the table in LDS. */
     int32_t mag_overlap;     /* nonzero: 50%-overlapping magnitude bins (Sec.
                                 2.3): bin j spans [j, j + 2) / (n_mag + 1) of
                                 the normalised magnitude u, i.e. with
@@ -215,7 +217,12 @@ typedef struct {
     int32_t precision;          /* GCE_PRECISION_* */
     int32_t trials_per_lane;    /* Pdot trials per lane actually used */
     int32_t lds_bytes_per_wave; /* LDS of one search wave */
-    int32_t table_in_lds;       /* the c ln c table is read from LDS */
+    int32_t table_in_lds;       /* where the c ln c table is read: 0 global
+                                   memory, 1 LDS, 2 global for the longer
+                                   curves and LDS in a second search launch
+                                   over the curves of at most
+                                   4 * n_phase * n_mag epochs (automatic
+                                   placement of a ragged batch) */
     int64_t work_units;         /* waves of one search launch */
     int64_t workspace_bytes;    /* device workspace held by the plan */
 } gce_plan_info_t;

@@ -167,16 +167,19 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
 // and the heuristics for what was left open.
 Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
                      const int64_t *off, int64_t n_curves, int32_t max_count,
-                     int requested_tq, int requested_placement)
+                     int requested_tq, int requested_placement, bool *tuned)
 {
+    *tuned = false;
     if (requested_tq == 0 && requested_placement == GCE_TABLE_AUTO) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         read_tune_file_locked();
         auto it = g_tuned.find(tune_key(precision, overlap, n_phase, n_mag, n_pd, off,
                                         n_curves));
         if (it != g_tuned.end() &&
-            gce::search_variant_exists(precision, n_phase, it->second.tq))
+            gce::search_variant_exists(precision, n_phase, it->second.tq)) {
+            *tuned = true;
             return it->second;
+        }
     }
     Tiling t{0, 0};
     t.tq = requested_tq > 0 ? requested_tq : heuristic_tq(precision, n_phase, n_pd, max_count);
@@ -194,6 +197,10 @@ struct gce_plan_s {
     gce_opts opts{};
     DevPlan dp{};
     int64_t total_points = 0;
+    // a second search launch over the shortest curves with the table in
+    // LDS: its first unit (0 = one launch) and count bound
+    int64_t split_unit = 0;
+    int32_t split_max_count = 0;
     std::vector<int64_t> off_host;
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -272,6 +279,38 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
     return (phase_overlap ? 1 : 0) | (mag_overlap ? 2 : 0);
 }
 
+// Ragged batches: the curves with many histogram cells per epoch (N at most
+// 4 n_phase n_mag, the automatic placement's own criterion) take a second
+// search launch with the table in LDS, sized for the longest of them, when
+// the batch as a whole keeps the table in global memory.  Measured on
+// MI355X, 8,192 curves of 50-3,000 epochs, 10 x 5 bins, 4 trials per lane
+// (kernel ms, global / LDS table): N <= 150: 16.4 / 11.8; 150 < N <= 600:
+// 63.5 / 68.9; N > 600: 100.6 / 157.1.  Returns the number of curves of the
+// first launch (the longest ones; the schedule is longest first), or 0 for
+// one launch; *short_max_count receives the second launch's count bound.
+int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase_overlap,
+                        int mag_overlap, const int64_t *off, int64_t n_curves,
+                        int32_t *short_max_count)
+{
+    const int64_t limit = 4 * (int64_t)n_phase * n_mag;
+    int64_t n_long = 0, short_max = 0;
+    for (int64_t c = 0; c < n_curves; ++c) {
+        const int64_t n = off[c + 1] - off[c];
+        if (n > limit) ++n_long;
+        else short_max = std::max(short_max, n);
+    }
+    if (n_long == 0 || n_long == n_curves) return 0;
+    int32_t mc = 0;
+    if (count_bound((int32_t)short_max, n_phase, phase_overlap, mag_overlap, &mc) != GCE_OK)
+        return 0;
+    if (mc > 1023 ||
+        gce::search_lds_bytes(precision, n_phase, tq, 1, mc) >
+            (size_t)gce::search_waves_per_block(1) * 20 * 1024)
+        return 0;
+    *short_max_count = mc;
+    return n_long;
+}
+
 }  // namespace
 
 extern "C" {
@@ -327,10 +366,11 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     int32_t max_count = 0;
     rc = count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
+    bool tuned = false;
     const Tiling tl = choose_tiling(o.precision, overlap_bits(o.phase_overlap, o.mag_overlap),
                                     n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
                                     n_curves, max_count, o.trials_per_lane,
-                                    o.table_placement);
+                                    o.table_placement, &tuned);
     const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
@@ -372,9 +412,17 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     dp.overlap = o.phase_overlap;
     dp.mag_overlap = o.mag_overlap;
     dp.lut_lds = tl.lut_lds;
+    dp.unit0 = 0;
     if (dp.n_units > gce::kMaxUnits) {
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
+    }
+    if (!tuned && o.trials_per_lane == 0 && o.table_placement == GCE_TABLE_AUTO &&
+        !tl.lut_lds) {
+        const int64_t n_long = split_by_length(o.precision, n_phase_bins, n_mag_bins, tq,
+                                               o.phase_overlap, o.mag_overlap, curve_offsets,
+                                               n_curves, &pl->split_max_count);
+        pl->split_unit = n_long * dp.units_per_curve;
     }
 
     // schedule: longest curves first (stable), so ragged batches drain evenly
@@ -445,6 +493,22 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     return GCE_OK;
 }
 
+// The search over the plan's work units: one launch, or with a length split
+// the longest curves (table as chosen) then the shortest (table in LDS).
+static hipError_t search_launches(const gce_plan_s *pl, void *out_ce, hipStream_t s)
+{
+    if (pl->split_unit <= 0) return gce::launch_search(pl->dp, out_ce, s);
+    DevPlan a = pl->dp;
+    a.n_units = pl->split_unit;
+    hipError_t e = gce::launch_search(a, out_ce, s);
+    if (e != hipSuccess) return e;
+    DevPlan b = pl->dp;
+    b.unit0 = pl->split_unit;
+    b.lut_lds = 1;
+    b.max_count = pl->split_max_count;
+    return gce::launch_search(b, out_ce, s);
+}
+
 int gce_plan_execute(gce_plan_t pl, const double *times, const double *mags,
                      const double *periods, const double *pdots, void *out_ce,
                      gce_best_t *out_best, void *stream)
@@ -465,7 +529,7 @@ int gce_plan_execute(gce_plan_t pl, const double *times, const double *mags,
     const size_t slot = timed ? (size_t)(pl->n_timed % (int64_t)pl->ev_start.size()) : 0;
     if (timed && (e = hipEventRecord(pl->ev_start[slot], s)) != hipSuccess)
         return fail_hip(e, "timing event");
-    e = gce::launch_search(dp, out_ce, s);
+    e = search_launches(pl, out_ce, s);
     if (e != hipSuccess) return fail_hip(e, "search launch");
     if (timed) {
         if ((e = hipEventRecord(pl->ev_stop[slot], s)) != hipSuccess)
@@ -560,7 +624,7 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
         gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds,
                               pl->dp.max_count) /
         gce::search_waves_per_block(pl->dp.lut_lds));
-    info->table_in_lds = pl->dp.lut_lds;
+    info->table_in_lds = pl->split_unit > 0 ? 2 : pl->dp.lut_lds;
     info->work_units = pl->dp.n_units;
     info->workspace_bytes = (int64_t)pl->ws_bytes;
     return GCE_OK;

@@ -50,7 +50,10 @@ struct DevPlan {
     int32_t n_qgroups;        // ceil(n_pd / tq)
     int64_t n_ptiles;         // ceil(n_p / 64)
     int64_t units_per_curve;  // n_qgroups * n_ptiles
-    int64_t n_units;          // n_curves * units_per_curve
+    int64_t n_units;          // n_curves * units_per_curve; for one search
+                              // launch: the end of its unit range
+    int64_t unit0;            // first work unit of a search launch (0 unless
+                              // the batch is searched in two launches)
     int32_t max_count;        // largest count of a histogram cell, a marginal
                               // or a pair of phase slots: the longest curve,
                               // doubled with overlapping magnitude bins and

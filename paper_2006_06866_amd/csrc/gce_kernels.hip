@@ -266,7 +266,7 @@ hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
     if (!v) return hipErrorInvalidValue;
     const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_count);
     const int wpb = search_waves_per_block(dp.lut_lds);
-    const int64_t blocks = (dp.n_units + wpb - 1) / wpb;
+    const int64_t blocks = (dp.n_units - dp.unit0 + wpb - 1) / wpb;
     const int64_t gx = blocks < kSearchGridX ? blocks : kSearchGridX;
     const int64_t gy = (blocks + gx - 1) / gx;
     hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave * wpb), lds, s,

@@ -74,8 +74,8 @@ void k_search(DevPlan dp, void *out_ce_v)
         __syncthreads();
     }
     // 2-D launch (a dispatch's grid size counts work-items in 32 bits):
-    // unit = (y * gridDim.x + x) * WPB + wave, in dispatch order
-    const int64_t u = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * WPB + wave;
+    // unit = unit0 + (y * gridDim.x + x) * WPB + wave, in dispatch order
+    const int64_t u = dp.unit0 + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * WPB + wave;
     if (u >= dp.n_units) return;
     const int64_t rank = u / dp.units_per_curve;
     const int64_t rem = u - rank * dp.units_per_curve;
