@@ -498,6 +498,39 @@ def test_automatic_table_placement():
     assert info([500] * 4, 50, 10, True)["table_in_lds"] == 1   # paper scale
     assert info([3000] * 4, 50, 10)["table_in_lds"] == 0        # table over 8 KiB
     assert info([100] * 4, 128, 5, n_pd=1)["table_in_lds"] == 0  # LDS budget
+    # ragged: the curves of at most 4 * 10 * 5 epochs get the LDS table
+    assert info([3000, 700, 201, 200, 50, 1], 10, 5)["table_in_lds"] == 2
+    assert info([200, 50, 1], 10, 5)["table_in_lds"] == 1       # all short
+
+
+@pytest.mark.parametrize("precision", [gce.PRECISION_FP64, gce.PRECISION_SPLIT_FP32])
+@pytest.mark.parametrize("phase_overlap,mag_overlap", [(False, False), (True, True)])
+def test_length_split_matches_one_placement(precision, phase_overlap, mag_overlap):
+    """A ragged batch searched in two launches (longer curves with the
+    table in global memory, the shortest with it in LDS) gives bit for bit
+    the cube and minima of the whole batch with the table in global memory
+    (both placements hold the same doubles and add them in the same order),
+    and the FP64 plan matches the oracle."""
+    lengths = [1200, 650, 300, 201, 200, 199, 120, 64, 63, 2, 1]
+    w = synth.random_curves(180 + precision + 2 * phase_overlap, lengths, n_freq=150,
+                            n_pdots=6, n_phase=10, n_mag=5, pdot_scale=5e-9)
+    split = run_gpu(w, precision=precision, phase_overlap=phase_overlap,
+                    mag_overlap=mag_overlap)
+    whole = run_gpu(w, precision=precision, phase_overlap=phase_overlap,
+                    mag_overlap=mag_overlap, table_placement=gce.TABLE_GLOBAL)
+    assert split[0].info()["table_in_lds"] == 2
+    assert torch.equal(split[2], whole[2])
+    assert torch.equal(split[3], whole[3])
+    if precision == gce.PRECISION_FP64:
+        oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5,
+                                     phase_overlap=phase_overlap, mag_overlap=mag_overlap)
+        cm = 2 if mag_overlap else 1
+        assert_cube_close(split[2].cpu().numpy(), oc, w, "length split", count_mult=cm)
+        bf = gce.best_fields(split[3])
+        assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "length split",
+                          count_mult=cm)
+    split[0].close()
+    whole[0].close()
 
 
 @pytest.mark.parametrize("n_phase", [3, 10, 50, 128])
