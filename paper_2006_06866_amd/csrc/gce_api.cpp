@@ -167,19 +167,16 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
 // and the heuristics for what was left open.
 Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
                      const int64_t *off, int64_t n_curves, int32_t max_count,
-                     int requested_tq, int requested_placement, bool *tuned)
+                     int requested_tq, int requested_placement)
 {
-    *tuned = false;
     if (requested_tq == 0 && requested_placement == GCE_TABLE_AUTO) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         read_tune_file_locked();
         auto it = g_tuned.find(tune_key(precision, overlap, n_phase, n_mag, n_pd, off,
                                         n_curves));
         if (it != g_tuned.end() &&
-            gce::search_variant_exists(precision, n_phase, it->second.tq)) {
-            *tuned = true;
+            gce::search_variant_exists(precision, n_phase, it->second.tq))
             return it->second;
-        }
     }
     Tiling t{0, 0};
     t.tq = requested_tq > 0 ? requested_tq : heuristic_tq(precision, n_phase, n_pd, max_count);
@@ -282,7 +279,8 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 // Ragged batches: the curves with many histogram cells per epoch (N at most
 // 4 n_phase n_mag, the automatic placement's own criterion) take a second
 // search launch with the table in LDS, sized for the longest of them, when
-// the batch as a whole keeps the table in global memory.  Measured on
+// the placement is automatic and the batch as a whole keeps the table in
+// global memory.  Measured on
 // MI355X, 8,192 curves of 50-3,000 epochs, 10 x 5 bins, 4 trials per lane
 // (kernel ms, global / LDS table): N <= 150: 16.4 / 11.8; 150 < N <= 600:
 // 63.5 / 68.9; N > 600: 100.6 / 157.1.  Returns the number of curves of the
@@ -366,11 +364,10 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     int32_t max_count = 0;
     rc = count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
-    bool tuned = false;
     const Tiling tl = choose_tiling(o.precision, overlap_bits(o.phase_overlap, o.mag_overlap),
                                     n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
                                     n_curves, max_count, o.trials_per_lane,
-                                    o.table_placement, &tuned);
+                                    o.table_placement);
     const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
@@ -417,8 +414,9 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         delete pl;
         return fail(GCE_EINVAL, "too many work units for one launch");
     }
-    if (!tuned && o.trials_per_lane == 0 && o.table_placement == GCE_TABLE_AUTO &&
-        !tl.lut_lds) {
+    // whenever the placement is automatic and the batch keeps the table in
+    // global memory (chosen by the heuristics or by tuning)
+    if (o.table_placement == GCE_TABLE_AUTO && !tl.lut_lds) {
         const int64_t n_long = split_by_length(o.precision, n_phase_bins, n_mag_bins, tq,
                                                o.phase_overlap, o.mag_overlap, curve_offsets,
                                                n_curves, &pl->split_max_count);
