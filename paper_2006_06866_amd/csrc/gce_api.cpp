@@ -280,12 +280,12 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 // 4 n_phase n_mag, the automatic placement's own criterion) take a second
 // search launch with the table in LDS, sized for the longest of them, when
 // the placement is automatic and the batch as a whole keeps the table in
-// global memory.  Measured on
-// MI355X, 8,192 curves of 50-3,000 epochs, 10 x 5 bins, 4 trials per lane
-// (kernel ms, global / LDS table): N <= 150: 16.4 / 11.8; 150 < N <= 600:
-// 63.5 / 68.9; N > 600: 100.6 / 157.1.  Returns the number of curves of the
-// first launch (the longest ones; the schedule is longest first), or 0 for
-// one launch; *short_max_count receives the second launch's count bound.
+// global memory.  Measured on MI355X, 8,192 curves of 50-3,000 epochs,
+// 10 x 5 bins, 4 trials per lane (kernel ms, global / LDS table):
+// N <= 150: 16.4 / 11.8; 150 < N <= 600: 63.5 / 68.9; N > 600: 100.6 / 157.1.
+// Returns the number of curves of the first launch (the longest ones; the
+// schedule is longest first), or 0 for one launch; *short_max_count receives
+// the second launch's count bound (below the whole plan's, which passed).
 int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase_overlap,
                         int mag_overlap, const int64_t *off, int64_t n_curves,
                         int32_t *short_max_count)
