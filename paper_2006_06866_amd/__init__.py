@@ -146,7 +146,14 @@ def best_fields(best: torch.Tensor) -> dict:
 
 
 class Plan:
-    """A validated, scheduled and allocated search shape (gce_plan_t)."""
+    """A validated, scheduled and allocated search shape (gce_plan_t).
+
+    offsets: host curve offsets [n_curves + 1]; precision: PRECISION_FP64
+    (bit-exact bins) or PRECISION_SPLIT_FP32; trials_per_lane: 0 (automatic)
+    or 1, 2, 4, 8; phase_overlap / mag_overlap: 50%-overlapping phase /
+    magnitude bins (Sec. 2.3); table_placement: TABLE_AUTO, TABLE_GLOBAL or
+    TABLE_LDS for the c ln c table.  Options map one to one onto gce_opts.
+    """
 
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
