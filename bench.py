@@ -356,9 +356,6 @@ def main():
                     help="time per light curve per search point over n_phase in {15, 50}, "
                          "N in {100, 1000}, 1e3..1e7 search points at n_Pdot 1 and 32 "
                          "(the axes of the paper's timing figure), one JSON line")
-    ap.add_argument("--valu-probe", action="store_true",
-                    help="run the VALU issue-cost probe (paper_2006_06866_amd/valu_probe) "
-                         "and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (the "
                          "known-size kernel that scales HBM byte counters)")
@@ -366,12 +363,6 @@ def main():
 
     if args.sweep:
         raise SystemExit(timing_sweep())
-    if args.valu_probe:
-        import subprocess
-        probe = os.path.join(ROOT, "paper_2006_06866_amd", "valu_probe")
-        if not os.path.exists(probe):
-            raise SystemExit(f"{probe} is missing: run __graft_entry__.build() first")
-        raise SystemExit(subprocess.call([probe]))
     if args.copy_calibration > 0:
         import torch
         n = args.copy_calibration * (1 << 20) // 4

@@ -13,7 +13,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgce.so")
-PROBE = os.path.join(PKG, "valu_probe")   # VALU issue-cost probe (bench.py --valu-probe)
 # command-line search over inputs in raw files, linked against libgce.so only
 FILE_SEARCH = os.path.join(PKG, "gce_file_search")
 # the search-kernel variants are spread over four files so they compile in
@@ -63,15 +62,11 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
                 f.result()
         tmp = LIB + ".tmp%d" % os.getpid()
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-        ptmp = PROBE + ".tmp%d" % os.getpid()
-        _run([HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-              "-packed-fp32-ops", os.path.join(CSRC, "valu_probe.hip"), "-o", ptmp], verbose)
         os.replace(tmp, LIB)
         ftmp = FILE_SEARCH + ".tmp%d" % os.getpid()
         _run([HIPCC, "-O2", "-std=c++17", "-Wall", "-I", INCLUDE,
               os.path.join(CSRC, "gce_file_search.cpp"), "-L", PKG, "-lgce",
               "-Wl,-rpath,$ORIGIN", "-o", ftmp], verbose)
-    os.replace(ptmp, PROBE)
     os.replace(ftmp, FILE_SEARCH)
     return LIB
 
