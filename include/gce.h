@@ -43,7 +43,14 @@
  *    [1e-12, 1e12] days or NaN, |Pdot| > 1 or NaN, epochs of one curve
  *    spanning more than 1e12 days) cannot be reported synchronously: the affected
  *    curves (all curves for a bad grid) get flat_index = -1, ce_min = NaN and
- *    NaN CE values.
+ *    NaN CE values.  Split-precision plans (GCE_PRECISION_SPLIT_FP32) square
+ *    x = (t - t0) / P in FP32 and accept only periods of at least 1e-6 days
+ *    and curves spanning at most 1e10 days (x below 1e16 cycles); other
+ *    values are bad data values in the same sense.
+ *  - Test hook: with the environment variable GCE_FAIL_ALLOC=1, the entry
+ *    points that allocate device memory (gce_plan_create, gce_search,
+ *    gce_autotune) return GCE_ENOMEM after checking their arguments, before
+ *    any device call.
  *  - Limits: 1 <= n_phase_bins <= 128, 1 <= n_mag_bins <= 255,
  *    1 <= points per curve <= 65535 (counts are 16-bit; overlapping bins
  *    that count an epoch twice halve this, see gce_opts).
@@ -97,9 +104,13 @@ typedef struct {
  *  out_best        : device, [n_curves] gce_best_t.
  *  stream          : hipStream_t.
  *
- * Allocates (once, cached per device and shape) a workspace; not safe to
- * call during stream capture unless an identical call has already run on
- * this device.  Returns GCE_OK or a negative GCE_E* code.
+ * Allocates a workspace once per device, stream and shape (a small cache of
+ * plans; the least recently used of more than four is destroyed, which
+ * synchronises the device).  Calls on one stream share that stream's plan and
+ * are ordered by the stream; calls on different streams never share a
+ * workspace.  Not safe to call during stream capture unless an identical
+ * call on the same stream has already run.  Returns GCE_OK or a negative
+ * GCE_E* code.
  */
 int gce_search(const double *times, const double *mags,
                const int64_t *curve_offsets, int64_t n_curves,

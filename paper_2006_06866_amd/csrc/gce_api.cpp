@@ -39,6 +39,16 @@ int fail_hip(hipError_t e, const char *what)
     return fail(GCE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Failure injection for tests of the out-of-memory paths: with the
+// environment variable GCE_FAIL_ALLOC set to 1, every entry point that would
+// allocate device memory fails with GCE_ENOMEM after validating its
+// arguments and before touching the device.
+bool alloc_failure_injected()
+{
+    const char *v = std::getenv("GCE_FAIL_ALLOC");
+    return v && std::strcmp(v, "1") == 0;
+}
+
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
     int prev = -1;
@@ -143,7 +153,11 @@ int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max
                (size_t)gce::search_waves_per_block(1) * 20 * 1024;
 }
 
-int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
+}  // namespace
+
+int gce::set_error(int code, const char *msg) { return fail(code, msg); }
+
+int gce::heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
 {
     // Pdot trials per lane: more trials share each epoch's x and x^2, but
     // every trial pair adds a histogram region of LDS and registers.
@@ -162,9 +176,20 @@ int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
     return tq;
 }
 
+bool gce::tiling_fits(int precision, int n_phase, int tq, int lut_lds, int32_t max_count)
+{
+    return gce::search_variant_exists(precision, n_phase, tq) &&
+           (!lut_lds || max_count <= gce::kMaxLdsTableCount) &&
+           gce::search_lds_bytes(precision, n_phase, tq, lut_lds, max_count) <= gce::kMaxLdsBytes;
+}
+
+namespace {
+
 // Tiling of a plan: an autotuned choice for the shape class when neither
-// trials per lane nor the table placement is requested, else the request
-// and the heuristics for what was left open.
+// trials per lane nor the table placement is requested (and the choice fits
+// this batch: a class is keyed by the median curve length, so a batch of the
+// same class may hold a curve too long for a tuned table in LDS), else the
+// request and the heuristics for what was left open.
 Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
                      const int64_t *off, int64_t n_curves, int32_t max_count,
                      int requested_tq, int requested_placement)
@@ -175,11 +200,11 @@ Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t
         auto it = g_tuned.find(tune_key(precision, overlap, n_phase, n_mag, n_pd, off,
                                         n_curves));
         if (it != g_tuned.end() &&
-            gce::search_variant_exists(precision, n_phase, it->second.tq))
+            gce::tiling_fits(precision, n_phase, it->second.tq, it->second.lut_lds, max_count))
             return it->second;
     }
     Tiling t{0, 0};
-    t.tq = requested_tq > 0 ? requested_tq : heuristic_tq(precision, n_phase, n_pd, max_count);
+    t.tq = requested_tq > 0 ? requested_tq : gce::heuristic_tq(precision, n_phase, n_pd, max_count);
     if (requested_placement == GCE_TABLE_GLOBAL) t.lut_lds = 0;
     else if (requested_placement == GCE_TABLE_LDS) t.lut_lds = 1;
     else t.lut_lds = heuristic_lut_lds(precision, n_phase, n_mag, t.tq, max_count,
@@ -222,9 +247,11 @@ uint64_t hash_offsets(const int64_t *off, int64_t n)
     return h;
 }
 
-int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
-                   int64_t n_pd, int32_t n_phase, int32_t n_mag,
-                   int32_t *max_n_out)
+}  // namespace
+
+int gce::validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
+                        int64_t n_pd, int32_t n_phase, int32_t n_mag,
+                        int32_t *max_n_out)
 {
     if (!off) return fail(GCE_EINVAL, "curve_offsets is NULL");
     if (n_curves < 1) return fail(GCE_EINVAL, "n_curves must be >= 1");
@@ -257,8 +284,8 @@ int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p,
 // up to 2N entries with overlapping magnitude bins, and a single overlapping
 // phase bin adds its one slot to itself.  Counts are 16-bit, so the bound must
 // stay at or below 65535.
-int count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap, int32_t mag_overlap,
-                int32_t *max_count_out)
+int gce::count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap,
+                     int32_t mag_overlap, int32_t *max_count_out)
 {
     int64_t m = max_n;
     if (mag_overlap) m *= 2;
@@ -270,6 +297,72 @@ int count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap, int32_t m
     *max_count_out = (int32_t)m;
     return GCE_OK;
 }
+
+void gce::fill_shape(DevPlan &dp, int64_t n_curves, int64_t n_p, int64_t n_pd,
+                     int32_t n_phase, int32_t n_mag, int32_t tq, int32_t max_count,
+                     const gce_opts &o, int32_t lut_lds)
+{
+    dp.n_curves = n_curves;
+    dp.n_p = n_p;
+    dp.n_pd = n_pd;
+    dp.n_phase = n_phase;
+    dp.n_mag = n_mag;
+    dp.tq = tq;
+    dp.n_qgroups = (int32_t)((n_pd + tq - 1) / tq);
+    dp.n_ptiles = (n_p + kWave - 1) / kWave;
+    dp.units_per_curve = (int64_t)dp.n_qgroups * dp.n_ptiles;
+    dp.n_units = n_curves * dp.units_per_curve;
+    dp.unit0 = 0;
+    dp.max_count = max_count;
+    dp.precision = o.precision;
+    dp.overlap = o.phase_overlap;
+    dp.mag_overlap = o.mag_overlap;
+    dp.lut_lds = lut_lds;
+}
+
+gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_points)
+{
+    const size_t A = 256;
+    size_t sz = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = sz;
+        sz = align_up(sz + bytes, A);
+        return at;
+    };
+    WorkspaceLayout L{};
+    L.off = take(sizeof(int64_t) * (size_t)(dp.n_curves + 1));
+    L.order = take(sizeof(int32_t) * (size_t)dp.n_curves);
+    L.lut = take(sizeof(double) * (size_t)(dp.max_count + 1));
+    L.dt = take(sizeof(double) * (size_t)total_points * (dp.mag_overlap ? 2 : 1));
+    L.seg = take(sizeof(int32_t) * (size_t)dp.n_curves * (size_t)(dp.n_mag + 1));
+    L.curve_ok = take(sizeof(int32_t) * (size_t)dp.n_curves);
+    L.grid_ok = take(sizeof(int32_t));
+    L.inv_p = take(sizeof(double) * (size_t)dp.n_p);
+    L.half_pd = take(sizeof(double) * (size_t)dp.n_pd);
+    L.half_pd32 = take(sizeof(float) * (size_t)dp.n_pd);
+    L.partials = take(sizeof(Partial) * (size_t)dp.n_units);
+    L.stats = take(sizeof(UnitStats) * (size_t)dp.n_units);
+    L.total = sz;
+    return L;
+}
+
+void gce::bind_workspace(DevPlan &dp, char *w, const WorkspaceLayout &L)
+{
+    dp.off = reinterpret_cast<const int64_t *>(w + L.off);
+    dp.order = reinterpret_cast<const int32_t *>(w + L.order);
+    dp.lut = reinterpret_cast<const double *>(w + L.lut);
+    dp.dt_sorted = reinterpret_cast<double *>(w + L.dt);
+    dp.seg = reinterpret_cast<int32_t *>(w + L.seg);
+    dp.curve_ok = reinterpret_cast<int32_t *>(w + L.curve_ok);
+    dp.grid_ok = reinterpret_cast<int32_t *>(w + L.grid_ok);
+    dp.inv_p = reinterpret_cast<double *>(w + L.inv_p);
+    dp.half_pd = reinterpret_cast<double *>(w + L.half_pd);
+    dp.half_pd32 = reinterpret_cast<float *>(w + L.half_pd32);
+    dp.partials = reinterpret_cast<Partial *>(w + L.partials);
+    dp.stats = reinterpret_cast<UnitStats *>(w + L.stats);
+}
+
+namespace {
 
 int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 {
@@ -299,7 +392,7 @@ int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase
     }
     if (n_long == 0 || n_long == n_curves) return 0;
     int32_t mc = 0;
-    if (count_bound((int32_t)short_max, n_phase, phase_overlap, mag_overlap, &mc) != GCE_OK)
+    if (gce::count_bound((int32_t)short_max, n_phase, phase_overlap, mag_overlap, &mc) != GCE_OK)
         return 0;
     if (mc > 1023 ||
         gce::search_lds_bytes(precision, n_phase, tq, 1, mc) >
@@ -344,8 +437,8 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     if (!plan_out) return fail(GCE_EINVAL, "plan pointer is NULL");
     *plan_out = nullptr;
     int32_t max_n = 0;
-    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
-                            n_phase_bins, n_mag_bins, &max_n);
+    int rc = gce::validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
+                                 n_phase_bins, n_mag_bins, &max_n);
     if (rc != GCE_OK) return rc;
     gce_opts o{};
     if (opts) o = *opts;
@@ -362,7 +455,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         o.table_placement != GCE_TABLE_LDS)
         return fail(GCE_EINVAL, "table_placement must be 0, 1 or 2");
     int32_t max_count = 0;
-    rc = count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
+    rc = gce::count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
     const Tiling tl = choose_tiling(o.precision, overlap_bits(o.phase_overlap, o.mag_overlap),
                                     n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
@@ -371,14 +464,23 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
-    if (tl.lut_lds && max_count > 8191)   // LDS-table counts are kept in units of 8
+    if (tl.lut_lds && max_count > gce::kMaxLdsTableCount)   // counts in units of 8
         return fail(GCE_EUNSUPPORTED,
                     "the table in LDS needs counts of at most 8191 (curves of at most "
                     "8191 epochs, half that with overlapping magnitude bins)");
-    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_count) > 64 * 1024)
+    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_count) >
+        gce::kMaxLdsBytes)
         return fail(GCE_EUNSUPPORTED,
                     "a wave's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
                     "table in global memory");
+
+    DevPlan shape{};
+    gce::fill_shape(shape, n_curves, n_periods, n_pdots, n_phase_bins, n_mag_bins, tq,
+                    max_count, o, tl.lut_lds);
+    if (shape.n_units > gce::kMaxUnits)
+        return fail(GCE_EINVAL, "too many work units for one launch");
+    if (alloc_failure_injected())
+        return fail(GCE_ENOMEM, "device allocation failure injected (GCE_FAIL_ALLOC=1)");
 
     rc = check_device(device);
     if (rc != GCE_OK) return rc;
@@ -394,26 +496,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     pl->key_hash = hash_offsets(curve_offsets, n_curves);
 
     DevPlan &dp = pl->dp;
-    dp.n_curves = n_curves;
-    dp.n_p = n_periods;
-    dp.n_pd = n_pdots;
-    dp.n_phase = n_phase_bins;
-    dp.n_mag = n_mag_bins;
-    dp.tq = tq;
-    dp.n_qgroups = (int32_t)((n_pdots + tq - 1) / tq);
-    dp.n_ptiles = (n_periods + gce::kWave - 1) / gce::kWave;
-    dp.units_per_curve = (int64_t)dp.n_qgroups * dp.n_ptiles;
-    dp.n_units = n_curves * dp.units_per_curve;
-    dp.max_count = max_count;
-    dp.precision = o.precision;
-    dp.overlap = o.phase_overlap;
-    dp.mag_overlap = o.mag_overlap;
-    dp.lut_lds = tl.lut_lds;
-    dp.unit0 = 0;
-    if (dp.n_units > gce::kMaxUnits) {
-        delete pl;
-        return fail(GCE_EINVAL, "too many work units for one launch");
-    }
+    dp = shape;
     // whenever the placement is automatic and the batch keeps the table in
     // global memory (chosen by the heuristics or by tuning)
     if (o.table_placement == GCE_TABLE_AUTO && !tl.lut_lds) {
@@ -431,48 +514,15 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
                (curve_offsets[b + 1] - curve_offsets[b]);
     });
 
-    // workspace layout
-    const size_t A = 256;
-    size_t sz = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = sz;
-        sz = align_up(sz + bytes, A);
-        return at;
-    };
-    const size_t o_off = take(sizeof(int64_t) * (size_t)(n_curves + 1));
-    const size_t o_order = take(sizeof(int32_t) * (size_t)n_curves);
-    const size_t o_lut = take(sizeof(double) * (size_t)(max_count + 1));
-    const size_t o_dt = take(sizeof(double) * (size_t)pl->total_points *
-                             (o.mag_overlap ? 2 : 1));
-    const size_t o_seg = take(sizeof(int32_t) * (size_t)n_curves * (size_t)(n_mag_bins + 1));
-    const size_t o_cok = take(sizeof(int32_t) * (size_t)n_curves);
-    const size_t o_gok = take(sizeof(int32_t));
-    const size_t o_invp = take(sizeof(double) * (size_t)n_periods);
-    const size_t o_hpd = take(sizeof(double) * (size_t)n_pdots);
-    const size_t o_hpd32 = take(sizeof(float) * (size_t)n_pdots);
-    const size_t o_part = take(sizeof(gce::Partial) * (size_t)dp.n_units);
-    const size_t o_stats = take(sizeof(gce::UnitStats) * (size_t)dp.n_units);
-    pl->ws_bytes = sz;
-
-    hipError_t e = hipMalloc(&pl->ws, sz);
+    const gce::WorkspaceLayout lay = gce::workspace_layout(dp, pl->total_points);
+    pl->ws_bytes = lay.total;
+    hipError_t e = hipMalloc(&pl->ws, lay.total);
     if (e != hipSuccess) {
         delete pl;
         (void)hipGetLastError();
         return fail(GCE_ENOMEM, "hipMalloc of the workspace failed");
     }
-    char *w = static_cast<char *>(pl->ws);
-    dp.off = reinterpret_cast<const int64_t *>(w + o_off);
-    dp.order = reinterpret_cast<const int32_t *>(w + o_order);
-    dp.lut = reinterpret_cast<const double *>(w + o_lut);
-    dp.dt_sorted = reinterpret_cast<double *>(w + o_dt);
-    dp.seg = reinterpret_cast<int32_t *>(w + o_seg);
-    dp.curve_ok = reinterpret_cast<int32_t *>(w + o_cok);
-    dp.grid_ok = reinterpret_cast<int32_t *>(w + o_gok);
-    dp.inv_p = reinterpret_cast<double *>(w + o_invp);
-    dp.half_pd = reinterpret_cast<double *>(w + o_hpd);
-    dp.half_pd32 = reinterpret_cast<float *>(w + o_hpd32);
-    dp.partials = reinterpret_cast<gce::Partial *>(w + o_part);
-    dp.stats = reinterpret_cast<gce::UnitStats *>(w + o_stats);
+    gce::bind_workspace(dp, static_cast<char *>(pl->ws), lay);
 
     e = hipMemcpy(const_cast<int64_t *>(dp.off), curve_offsets,
                   sizeof(int64_t) * (size_t)(n_curves + 1), hipMemcpyHostToDevice);
@@ -705,8 +755,12 @@ int gce_plan_destroy(gce_plan_t pl)
 // ---------------------------------------------------------------------------
 namespace {
 
+// Keyed by stream too: calls on different streams never share a workspace
+// (overlapping searches on two streams would race on it), while calls on one
+// stream are ordered by the stream itself.
 struct CacheEntry {
     int device;
+    void *stream;
     int64_t n_curves, n_p, n_pd;
     int32_t n_phase, n_mag;
     uint64_t hash;
@@ -727,11 +781,13 @@ extern "C" int gce_search(const double *times, const double *mags,
                           double *out_ce, gce_best_t *out_best, void *stream)
 {
     int32_t max_n = 0;
-    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
-                            n_phase_bins, n_mag_bins, &max_n);
+    int rc = gce::validate_shape(curve_offsets, n_curves, n_periods, n_pdots,
+                                 n_phase_bins, n_mag_bins, &max_n);
     if (rc != GCE_OK) return rc;
     if (!times || !mags || !periods || !pdots || !out_best)
         return fail(GCE_EINVAL, "NULL input or output pointer");
+    if (alloc_failure_injected())
+        return fail(GCE_ENOMEM, "device allocation failure injected (GCE_FAIL_ALLOC=1)");
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(GCE_ENODEV, "hipGetDevice failed");
     const uint64_t h = hash_offsets(curve_offsets, n_curves);
@@ -739,7 +795,8 @@ extern "C" int gce_search(const double *times, const double *mags,
     std::lock_guard<std::mutex> lock(g_cache_mu);
     gce_plan_t plan = nullptr;
     for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
-        if (it->device == dev && it->n_curves == n_curves && it->n_p == n_periods &&
+        if (it->device == dev && it->stream == stream && it->n_curves == n_curves &&
+            it->n_p == n_periods &&
             it->n_pd == n_pdots && it->n_phase == n_phase_bins &&
             it->n_mag == n_mag_bins && it->hash == h &&
             std::equal(curve_offsets, curve_offsets + n_curves + 1,
@@ -753,7 +810,7 @@ extern "C" int gce_search(const double *times, const double *mags,
         rc = gce_plan_create(&plan, curve_offsets, n_curves, n_periods, n_pdots,
                              n_phase_bins, n_mag_bins, nullptr, dev);
         if (rc != GCE_OK) return rc;
-        g_cache.push_front(CacheEntry{dev, n_curves, n_periods, n_pdots,
+        g_cache.push_front(CacheEntry{dev, stream, n_curves, n_periods, n_pdots,
                                       n_phase_bins, n_mag_bins, h, plan});
         while (g_cache.size() > kCacheMax) {
             gce_plan_destroy(g_cache.back().plan);
@@ -774,8 +831,8 @@ extern "C" int gce_autotune(const double *times, const double *mags,
                             int32_t *best_tq, int32_t *best_placement, float *ms)
 {
     int32_t max_n = 0;
-    int rc = validate_shape(curve_offsets, n_curves, n_periods, n_pdots, n_phase_bins,
-                            n_mag_bins, &max_n);
+    int rc = gce::validate_shape(curve_offsets, n_curves, n_periods, n_pdots, n_phase_bins,
+                                 n_mag_bins, &max_n);
     if (rc != GCE_OK) return rc;
     if (!times || !mags || !periods || !pdots || !best_tq)
         return fail(GCE_EINVAL, "NULL pointer");
@@ -786,8 +843,10 @@ extern "C" int gce_autotune(const double *times, const double *mags,
     if (mag_overlap != 0 && mag_overlap != 1)
         return fail(GCE_EINVAL, "mag_overlap must be 0 or 1");
     int32_t max_count = 0;
-    rc = count_bound(max_n, n_phase_bins, phase_overlap, mag_overlap, &max_count);
+    rc = gce::count_bound(max_n, n_phase_bins, phase_overlap, mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
+    if (alloc_failure_injected())
+        return fail(GCE_ENOMEM, "device allocation failure injected (GCE_FAIL_ALLOC=1)");
     rc = check_device(device);
     if (rc != GCE_OK) return rc;
     DeviceGuard guard(device);

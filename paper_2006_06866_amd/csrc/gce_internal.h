@@ -19,6 +19,15 @@ constexpr double kMaxSpanDays = 1e12;
 constexpr double kMinPeriod = 1e-12;
 constexpr double kMaxPeriod = 1e12;
 constexpr double kMaxAbsPdot = 1.0;
+// The split path squares x = (t - t0) / P in FP32: its plans keep x below
+// 1e16 cycles (x^2 < 1e32, far inside the float range) by accepting
+// periods of at least 1e-6 days and curves spanning at most 1e10 days.
+constexpr double kSplitMinPeriod = 1e-6;
+constexpr double kSplitMaxSpanDays = 1e10;
+// Largest count with the c ln c table in LDS: counts are kept in units of 8
+// in 16-bit halves.
+constexpr int32_t kMaxLdsTableCount = 8191;
+constexpr size_t kMaxLdsBytes = 64 * 1024;   // LDS of one search block
 // Search launches are 2-D: at most this many one-wave blocks along x (the
 // dispatch grid size counts work-items in 32 bits), up to 65,535 rows.
 constexpr int64_t kSearchGridX = 65536;
@@ -122,5 +131,37 @@ inline int search_waves_per_block(int lut_lds) { return lut_lds ? kLutWaves : 1;
 // Bytes of LDS one search block uses (lut_lds: the c ln c table of
 // max_count + 1 entries is kept in LDS too, once per block).
 size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count);
+// Fill dp.order[rank] = rank (the identity schedule) on `s`.
+hipError_t launch_iota_order(const DevPlan &dp, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// host-side plan construction (gce_api.cpp), shared by the entry points
+// ---------------------------------------------------------------------------
+// Byte offsets of the parts of a plan's device workspace (one block).
+struct WorkspaceLayout {
+    size_t off, order, lut, dt, seg, curve_ok, grid_ok, inv_p, half_pd, half_pd32,
+        partials, stats, total;
+};
+
+// Record `msg` as the calling thread's last error text; returns `code`.
+int set_error(int code, const char *msg);
+// Host checks of a shape: offsets, counts, bin counts, grid sizes.  On
+// success *max_n receives the longest curve's length.
+int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p, int64_t n_pd,
+                   int32_t n_phase, int32_t n_mag, int32_t *max_n);
+// Largest count of a histogram cell, a marginal or a pair of phase slots.
+int count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap, int32_t mag_overlap,
+                int32_t *max_count);
+// Pdot trials per lane chosen by the measured heuristic.
+int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count);
+// Whether a tiling has a kernel and fits the LDS and count limits.
+bool tiling_fits(int precision, int n_phase, int tq, int lut_lds, int32_t max_count);
+// Fill the shape fields of dp (pointers untouched).
+void fill_shape(DevPlan &dp, int64_t n_curves, int64_t n_p, int64_t n_pd, int32_t n_phase,
+                int32_t n_mag, int32_t tq, int32_t max_count, const gce_opts &o, int32_t lut_lds);
+// Workspace layout of a filled shape holding total_points epochs.
+WorkspaceLayout workspace_layout(const DevPlan &dp, int64_t total_points);
+// Point dp's workspace views into the block at `base`.
+void bind_workspace(DevPlan &dp, char *base, const WorkspaceLayout &lay);
 
 }  // namespace gce

@@ -44,10 +44,11 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_setup(DevPlan dp,
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double p_min = dp.precision == kPrecSplit ? kSplitMinPeriod : kMinPeriod;
     bool bad = false;
     for (int64_t p = i0; p < dp.n_p; p += stride) {
         const double P = periods[p];
-        const bool ok = P >= kMinPeriod && P <= kMaxPeriod;  // false for NaN
+        const bool ok = P >= p_min && P <= kMaxPeriod;       // false for NaN
         bad |= !ok;
         dp.inv_p[p] = ok ? 1.0 / P : 1.0;
     }
@@ -159,7 +160,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     mlo = block_reduce(mlo, true, red);
     mhi = block_reduce(mhi, false, red);
     __syncthreads();
-    const bool ok = !bad_sh && (tmax - tmin) <= kMaxSpanDays;
+    const double max_span = dp.precision == kPrecSplit ? kSplitMaxSpanDays : kMaxSpanDays;
+    const bool ok = !bad_sh && (tmax - tmin) <= max_span;
     const double t0 = tmin;
     const bool flat_mag = !(mhi > mlo);
 
@@ -213,6 +215,20 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
         }
         __syncthreads();
     }
+}
+
+// identity schedule: rank r searches curve r
+__global__ void k_iota_order(int32_t *order, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) order[i] = (int32_t)i;
+}
+
+hipError_t launch_iota_order(const DevPlan &dp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota_order, dim3((unsigned)((dp.n_curves + 255) / 256)), dim3(256),
+                       0, s, const_cast<int32_t *>(dp.order), dp.n_curves);
+    return hipGetLastError();
 }
 
 hipError_t launch_prepass(const DevPlan &dp, const double *times,
@@ -390,8 +406,9 @@ __global__ __launch_bounds__(64) void k_debug_counts(
                 b = (int)(split_slot_bits(sp, ha32, (float)nph) - kRoundMagicBits);
                 if (b == nph) b = 0;   // wrap slot
             }
-            b = b < 0 ? 0 : (b >= nph ? nph - 1 : b);
-            o[(int64_t)j * nph + b] += 1;
+            // a slot outside [0, n_phase) is not counted, so that the row
+            // totals show it
+            if (b >= 0 && b < nph) o[(int64_t)j * nph + b] += 1;
         }
         if (dp.overlap) {   // bin b spans disjoint bins b and b + 1 (mod n)
             uint32_t *row = o + (int64_t)j * nph;

@@ -159,3 +159,34 @@ def test_file_search_program_rejects_bad_use_on_host(tmp_path):
         f.write(b"\0" * 8)   # one magnitude too many
     r = subprocess.run([exe, str(tmp_path), "10", "5"], capture_output=True, text=True)
     assert r.returncode == 1 and "inconsistent" in r.stderr
+
+
+def test_injected_allocation_failure(monkeypatch):
+    """GCE_FAIL_ALLOC=1 makes every allocating entry point return GCE_ENOMEM
+    after its argument checks and before any device call; argument errors
+    still come first."""
+    _ensure_built()
+    L = gce.lib()
+    off = np.array([0, 5, 9], dtype=np.int64)
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    monkeypatch.setenv("GCE_FAIL_ALLOC", "1")
+    with pytest.raises(gce.GceError) as ei:
+        gce.Plan(off, 10, 2, 10, 5, device="cuda:0")
+    assert ei.value.status == -2
+    assert b"GCE_FAIL_ALLOC" in L.gce_status_string(-2)
+    with pytest.raises(gce.GceError) as ei:   # a bad shape is still EINVAL
+        gce.Plan(off, 10, 2, 129, 5, device="cuda:0")
+    assert ei.value.status == -1
+    dummy = ctypes.c_void_p(16)   # never dereferenced: the call fails first
+    rc = L.gce_search(dummy, dummy, offp, 2, dummy, 10, dummy, 2, 10, 5, None, dummy, None)
+    assert rc == -2
+    tq, pl = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = L.gce_autotune(dummy, dummy, offp, 2, dummy, 10, dummy, 2, 10, 5, 0, 0, 0, 0, None,
+                        ctypes.byref(tq), ctypes.byref(pl), None)
+    assert rc == -2
+    monkeypatch.setenv("GCE_FAIL_ALLOC", "0")
+    import torch
+    if not torch.cuda.is_available():   # without the injection: no device here
+        with pytest.raises(gce.GceError) as ei:
+            gce.Plan(off, 10, 2, 10, 5, device="cuda:0")
+        assert ei.value.status == -5

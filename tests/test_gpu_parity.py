@@ -777,3 +777,88 @@ def test_tune_cache_file_persists_overlap_choices(tmp_path):
     assert r2.returncode == 0, r2.stderr[-2000:]
     info = json.loads(r2.stdout.strip().splitlines()[-1])
     assert (info["trials_per_lane"], info["table_in_lds"]) == planted
+
+
+_TUNE_LONG_CHILD = r"""
+import json, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2006_06866_amd as gce
+from paper_2006_06866_amd import synth
+# nine curves of 300 epochs and one of 9,000: median length class 1 (< 512),
+# like the planted tuned line, but a count bound above the 8191 that the
+# table in LDS allows
+w = synth.random_curves(41, [300] * 9 + [9000], n_freq=96, n_pdots=2)
+dev = torch.device("cuda:0")
+t, m, P, Pd = (torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
+plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag, device=dev)
+info = plan.info()
+_, best = plan.execute(t, m, P, Pd)
+torch.cuda.synchronize()
+plan.close()
+_, best2 = gce.search(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, want_cube=False)
+torch.cuda.synchronize()
+info["flat"] = gce.best_fields(best)["flat_index"].tolist()
+info["flat_search"] = gce.best_fields(best2)["flat_index"].tolist()
+print(json.dumps(info), flush=True)
+"""
+
+
+def test_tuned_table_in_lds_not_taken_when_the_batch_does_not_fit(tmp_path):
+    """A tuned choice is per shape class (keyed by the median curve length):
+    a batch of that class holding one curve too long for the table in LDS
+    falls back to the heuristics instead of failing, through both the plan
+    and gce_search."""
+    import json
+    import os
+    import subprocess
+    import sys
+    from paper_2006_06866_amd import synth
+    cache = tmp_path / "tune.txt"
+    # precision 0, no overlap, 10 x 5 bins, 2 Pdots (class 1), median class 1,
+    # 4 trials per lane, table in LDS
+    cache.write_text("0 0 10 5 1 1 4 1\n")
+    env = dict(os.environ, GCE_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("[tune long] plan child")
+    r = subprocess.run([sys.executable, "-c", _TUNE_LONG_CHILD, root], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    info = json.loads(r.stdout.strip().splitlines()[-1])
+    assert info["table_in_lds"] != 1, info
+    w = synth.random_curves(41, [300] * 9 + [9000], n_freq=96, n_pdots=2)
+    _, obf, _ = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
+                              w.n_mag, want_cube=False)
+    assert info["flat"] == obf.tolist()
+    assert info["flat_search"] == obf.tolist()
+
+
+def test_gce_search_on_two_streams_does_not_share_a_workspace():
+    """Two gce_search calls of one shape enqueued back to back on two streams
+    (no synchronisation between them) each return their own inputs' results:
+    the cached plans are per stream."""
+    import torch
+    from paper_2006_06866_amd import synth
+    wa = synth.make_config(2).subset(np.arange(32))
+    wb = synth.make_config(2).subset(np.arange(32, 64))
+    assert np.array_equal(wa.offsets, wb.offsets)
+    da, db = upload(wa), upload(wb)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ref = []
+    for d, w in ((da, wa), (db, wb)):   # sequential reference on the current stream
+        _, b = gce.search(d[0], d[1], w.offsets, d[2], d[3], w.n_phase, w.n_mag,
+                          want_cube=False)
+        torch.cuda.synchronize()
+        ref.append(gce.best_fields(b))
+    torch.cuda.synchronize()
+    say("[two streams] concurrent")
+    for rep in range(3):
+        _, ba = gce.search(da[0], da[1], wa.offsets, da[2], da[3], wa.n_phase, wa.n_mag,
+                           want_cube=False, stream=sa)
+        _, bb = gce.search(db[0], db[1], wb.offsets, db[2], db[3], wb.n_phase, wb.n_mag,
+                           want_cube=False, stream=sb)
+        torch.cuda.synchronize()
+        for b, r in ((ba, ref[0]), (bb, ref[1])):
+            f = gce.best_fields(b)
+            assert np.array_equal(f["flat_index"], r["flat_index"]), rep
+            assert np.array_equal(f["ce_min"], r["ce_min"]), rep

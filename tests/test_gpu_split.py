@@ -173,3 +173,42 @@ def test_split_random_shapes_self_consistent():
         plan.close()
         ran += 1
     assert ran >= 15
+
+
+def test_split_range_limits_mark_curves_invalid():
+    """The split path squares x = (t - t0) / P in FP32, so its plans take
+    periods of at least 1e-6 d and spans of at most 1e10 d: a shorter period
+    invalidates the grid (every curve), a longer span its curve, where the
+    FP64 path accepts both.  Debug counts of valid split trials still total
+    the curve's epochs."""
+    w = synth.random_curves(71, [30, 40, 50], n_freq=16, n_pdots=2)
+    wp = synth.Workload(w.name, w.times, w.mags, w.offsets, w.periods.copy(), w.pdots,
+                        w.n_phase, w.n_mag)
+    wp.periods[5] = 5e-7
+    for prec, valid in ((gce.PRECISION_FP64, True), (gce.PRECISION_SPLIT_FP32, False)):
+        t, m, P, Pd = upload(wp)
+        plan = gce.Plan(wp.offsets, wp.periods.size, wp.pdots.size, wp.n_phase, wp.n_mag,
+                        precision=prec)
+        _, best = plan.execute(t, m, P, Pd)
+        torch.cuda.synchronize()
+        bf = gce.best_fields(best)
+        assert np.all((bf["flat_index"] >= 0) == valid), (prec, bf["flat_index"])
+        plan.close()
+    ws = synth.Workload(w.name, w.times.copy(), w.mags, w.offsets, w.periods, w.pdots,
+                        w.n_phase, w.n_mag)
+    ws.times[ws.offsets[1]] -= 2e10   # curve 1 spans over 2e10 days
+    for prec, want in ((gce.PRECISION_FP64, [True, True, True]),
+                       (gce.PRECISION_SPLIT_FP32, [True, False, True])):
+        t, m, P, Pd = upload(ws)
+        plan = gce.Plan(ws.offsets, ws.periods.size, ws.pdots.size, ws.n_phase, ws.n_mag,
+                        precision=prec)
+        _, best = plan.execute(t, m, P, Pd)
+        torch.cuda.synchronize()
+        bf = gce.best_fields(best)
+        assert (bf["flat_index"] >= 0).tolist() == want, (prec, bf["flat_index"])
+        if prec == gce.PRECISION_SPLIT_FP32:
+            ci = np.array([0, 2, 0, 2])
+            fi = np.array([0, 5, 17, 31])
+            cnt = plan.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy()
+            assert np.array_equal(cnt.sum(axis=(1, 2)), ws.lengths[ci])
+        plan.close()
