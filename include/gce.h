@@ -18,9 +18,10 @@
  *  - Units: epochs and periods in days, Pdot dimensionless.
  *  - t0 is the earliest epoch of each curve.  Magnitudes are normalised per
  *    curve onto [0, 1] by their minimum and maximum (u = (m - min) / (max -
- *    min), correctly rounded) and cut into n_mag equal bins, bin
- *    min((int)(u * n_mag), n_mag - 1) (the maximum falls in the last bin; a
- *    constant curve has one bin).
+ *    min), each operation correctly rounded) and cut into n_mag equal bins:
+ *    bin floor(u * n_mag) of the exact product (not of its rounding), at
+ *    most n_mag - 1 (the maximum falls in the last bin; a constant curve has
+ *    one bin).
  *  - Fold arithmetic is IEEE binary64 in this order: invP = 1.0 / P
  *    (correctly rounded), x = dt * invP, x2 = x * x,
  *    y = fma(-(0.5 * Pdot), x2, x), phi = y - floor(y); the phase bin is the
@@ -146,7 +147,8 @@ typedef struct {
     int32_t mag_overlap;     /* nonzero: 50%-overlapping magnitude bins (Sec.
                                 2.3): bin j spans [j, j + 2) / (n_mag + 1) of
                                 the normalised magnitude u, i.e. with
-                                s = min((int)(u * (n_mag + 1)), n_mag) the
+                                s = min(floor(u * (n_mag + 1)), n_mag) (the
+                                floor of the exact product) the
                                 epoch is in bins s - 1 and s where they exist
                                 (one bin in the first and last half-bin).  The
                                 probabilities of Eq. (4) are counts over the

@@ -26,7 +26,10 @@
  *     Probabilities of Eq. (4) are counts over the total count of the
  *     histogram (the same divisor as N, or 2N, without magnitude overlap);
  *   - the phase bin is floor(phi * n_phase) of the exact product (the
- *     computed phase phi itself is the rounded fold of Eq. (3));
+ *     computed phase phi itself is the rounded fold of Eq. (3)), and the
+ *     magnitude bin likewise floor(u * n_mag) of the exact product with the
+ *     normalised magnitude u (itself a rounded quotient): equal-width bins
+ *     of the value at hand, not of a rounding of the product;
  *   - empty histogram cells contribute nothing to Eq. (4);
  *   - the minimum over the grid is the first strict minimum in flat order
  *     flat = q * n_periods + p (Pdot index q outer, period index p inner);
@@ -48,6 +51,27 @@
 #define ORACLE_OK 0
 #define ORACLE_EINVAL (-1)
 #define ORACLE_ENOMEM (-2)
+
+/* ---------------------------------------------------------------------------
+ * Equal-width bins of [0, 1] (Sec. 2.3): value v in [0, 1] lies in bin
+ * floor(v * n), the floor taken of the exact product: v * n is split into its
+ * rounded value p and the exact remainder v*n - p (one fused multiply-add,
+ * the error-free product of Ogita, Rump and Oishi 2005), and a product that
+ * rounds up onto an integer is moved back below it.  v = 1 (and a v that
+ * rounds up to 1) falls in the last bin.
+ * ------------------------------------------------------------------------- */
+static int32_t equal_width_bin(double v, int32_t n_bins)
+{
+    double n = (double)n_bins;
+    double p = v * n;
+    double f = floor(p);
+    /* floor(p) is the exact floor unless p rounded up onto an integer */
+    if (f == p && fma(v, n, -p) < 0.0)   /* v * n == p + remainder */
+        f -= 1.0;
+    int32_t b = (int32_t)f;
+    if (b >= n_bins) b = n_bins - 1;
+    return b;
+}
 
 /* ---------------------------------------------------------------------------
  * Sec. 2.3: magnitudes normalised per light curve, then binned into n_mag
@@ -83,13 +107,11 @@ int ce_oracle_mag_bins2(const double *mags, int64_t n, int32_t n_mag,
         }
         double u = (mags[k] - lo) / (hi - lo); /* normalised to [0, 1] */
         if (!overlap) {
-            int32_t j = (int32_t)(u * (double)n_mag);
-            if (j >= n_mag) j = n_mag - 1;      /* m == m_max */
-            bin[k] = j;
+            bin[k] = equal_width_bin(u, n_mag);  /* m == m_max: last bin */
             continue;
         }
-        int32_t s = (int32_t)(u * (double)(n_mag + 1)); /* sub-interval */
-        if (s > n_mag) s = n_mag;                       /* m == m_max */
+        /* sub-interval of width 1 / (n_mag + 1); m == m_max: the last one */
+        int32_t s = equal_width_bin(u, n_mag + 1);
         if (s == 0) {                 /* first half-bin: bin 0 only */
             bin[k] = 0;
         } else if (s == n_mag) {      /* last half-bin: bin n_mag - 1 only */
@@ -111,23 +133,12 @@ int ce_oracle_mag_bins(const double *mags, int64_t n, int32_t n_mag,
 
 /* ---------------------------------------------------------------------------
  * Sec. 2.3: n_phase equal-width phase bins; phase phi lies in bin
- * floor(phi * n_phase).  The floor is taken of the exact product: phi * n is
- * split into its rounded value p and the exact remainder e = phi*n - p (one
- * fused multiply-add, the error-free product of Ogita, Rump and Oishi 2005),
- * and a product that rounds up onto an integer is moved back below it.  A
- * phase that rounds up to 1 falls in the last bin.
+ * floor(phi * n_phase) of the exact product.  A phase that rounds up to 1
+ * falls in the last bin.
  * ------------------------------------------------------------------------- */
 static int32_t phase_bin(double phi, int32_t n_phase)
 {
-    double n = (double)n_phase;
-    double p = phi * n;
-    double f = floor(p);
-    /* floor(p) is the exact floor unless p rounded up onto an integer */
-    if (f == p && fma(phi, n, -p) < 0.0)   /* phi * n == p + remainder */
-        f -= 1.0;
-    int32_t b = (int32_t)f;
-    if (b >= n_phase) b = n_phase - 1;
-    return b;
+    return equal_width_bin(phi, n_phase);
 }
 
 /* ---------------------------------------------------------------------------

@@ -66,7 +66,9 @@ struct DeviceGuard {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-int check_device(int dev)
+}  // namespace
+
+int gce::check_device(int dev)
 {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
@@ -81,6 +83,10 @@ int check_device(int dev)
                                     ", the library is built for gfx950 only");
     return GCE_OK;
 }
+
+namespace {
+
+using gce::check_device;
 
 // ---------------------------------------------------------------------------
 // tiling choice: autotuned per shape class, else a measured heuristic

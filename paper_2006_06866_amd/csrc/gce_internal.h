@@ -145,6 +145,8 @@ struct WorkspaceLayout {
 
 // Record `msg` as the calling thread's last error text; returns `code`.
 int set_error(int code, const char *msg);
+// GCE_OK if `dev` is a gfx950 device, else GCE_ENODEV (with the reason).
+int check_device(int dev);
 // Host checks of a shape: offsets, counts, bin counts, grid sizes.  On
 // success *max_n receives the longest curve's length.
 int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p, int64_t n_pd,

@@ -107,15 +107,22 @@ struct MagBins {
     int32_t first, second;
 };
 
+// floor(u * n) of the exact product, at most n - 1: the rounded product is
+// right unless it rounded up onto an integer, which the sign of the exact
+// remainder u * n - p (one fma) tells.
+__device__ __forceinline__ int32_t floor_product_bin(double u, int32_t n)
+{
+    const double nd = (double)n;
+    const double p = u * nd;
+    int32_t b = (int32_t)p;   // u >= 0: truncation is the floor of p
+    if ((double)b == p && __builtin_fma(u, nd, -p) < 0.0) --b;
+    return b < n ? b : n - 1;
+}
+
 __device__ __forceinline__ MagBins magnitude_bins(double u, int32_t n_mag, bool overlap)
 {
-    if (!overlap) {
-        int32_t j = (int32_t)(u * (double)n_mag);
-        if (j >= n_mag) j = n_mag - 1;
-        return MagBins{j, kNoBin};
-    }
-    int32_t s = (int32_t)(u * (double)(n_mag + 1));
-    if (s > n_mag) s = n_mag;
+    if (!overlap) return MagBins{floor_product_bin(u, n_mag), kNoBin};
+    const int32_t s = floor_product_bin(u, n_mag + 1);
     if (s == 0) return MagBins{0, kNoBin};
     if (s == n_mag) return MagBins{n_mag - 1, kNoBin};
     return MagBins{s - 1, s};

@@ -862,3 +862,33 @@ def test_gce_search_on_two_streams_does_not_share_a_workspace():
             f = gce.best_fields(b)
             assert np.array_equal(f["flat_index"], r["flat_index"]), rep
             assert np.array_equal(f["ce_min"], r["ce_min"]), rep
+
+
+@pytest.mark.parametrize("n_mag,mag_overlap", [(10, False), (7, False), (50, False),
+                                               (255, False), (10, True), (19, True)])
+def test_magnitude_bins_on_bin_edges_are_exact_floor(n_mag, mag_overlap):
+    """Normalised magnitudes on the doubles around every edge k / n (minimum
+    0, maximum 1), including those whose rounded product u * n lands on the
+    edge from below: the prepass bins each at the floor of the exact product,
+    like the oracle (whole histograms compared, magnitude rows included)."""
+    import math
+    from fractions import Fraction
+    n_sub = n_mag + 1 if mag_overlap else n_mag
+    us = {0.0, 1.0}
+    for k in range(1, n_sub):
+        e = k / n_sub
+        for v in (e, math.nextafter(e, 0.0), math.nextafter(e, 1.0),
+                  math.nextafter(math.nextafter(e, 0.0), 0.0)):
+            us.add(v)
+    m = np.array(sorted(us))
+    if not mag_overlap:   # the truncated rounded product would move some up
+        exact = [min(math.floor(Fraction(v) * n_mag), n_mag - 1) for v in m]
+        assert exact != [min(int(v * n_mag), n_mag - 1) for v in m]
+    rng = np.random.default_rng(n_mag)
+    t = np.sort(rng.uniform(0.0, 500.0, m.size))
+    off = np.array([0, m.size], dtype=np.int64)
+    w = synth.Workload("mag edges", t, rng.permutation(m), off,
+                       synth.frequency_grid_periods(5.0, 50.0, 70), np.array([0.0, 1e-9]),
+                       10, n_mag, mag_overlap=mag_overlap)
+    _full_parity(w, f"magnitude edges n_mag={n_mag} overlap={mag_overlap}",
+                 counts_sample=40, mag_overlap=mag_overlap)

@@ -575,3 +575,55 @@ def test_mag_overlap_search_consistent_with_counts():
                 assert np.array_equal(cnt.sum(axis=1), (2 if po else 1) * rows)
                 assert oracle.entropy(cnt) == cube[c, q, p]
             assert bf[c] == int(np.argmin(cube[c].ravel()))
+
+
+def _adversarial_normalised(n_bins_list, per_edge=3):
+    """Doubles u in (0, 1) just below bin edges k / n whose rounded product
+    fl(u * n) is the integer k while the exact product is below it, and their
+    neighbours: the cases where truncating the rounded product and flooring
+    the exact one disagree."""
+    out = set()
+    for n in n_bins_list:
+        for k in range(1, n):
+            u = k / n   # the double nearest k / n
+            for _ in range(per_edge):
+                out.add(u)
+                u = np.nextafter(u, 0.0)
+            u = k / n
+            for _ in range(per_edge):
+                u = np.nextafter(u, 1.0)
+                out.add(u)
+    return sorted(out)
+
+
+def test_mag_bins_floor_the_exact_product():
+    """Sec. 2.3's equal-width magnitude bins of the normalised magnitude u:
+    bin floor(u * n_mag) of the exact product, from exact rationals, on the
+    doubles around every edge k / n (minimum 0 and maximum 1, so u is the
+    magnitude itself), including those whose rounded product lands on the
+    edge from below (fl(0.3) * 10 rounds to 3; the exact product is below)."""
+    ns = [2, 3, 5, 6, 7, 10, 11, 20, 49, 50, 255]
+    us = _adversarial_normalised(ns)
+    m = np.array([0.0, 1.0] + us)
+    hits = 0
+    for n_mag in ns:
+        got = oracle.mag_bins(m, n_mag)
+        for k, u in enumerate(m):
+            want = min(math.floor(Fraction(float(u)) * n_mag), n_mag - 1)
+            assert got[k] == want, (n_mag, float(u), int(got[k]), want)
+            hits += int(float(u) * n_mag == math.floor(float(u) * n_mag) and
+                        Fraction(float(u)) * n_mag < float(u) * n_mag)
+    assert hits > 20   # the rounded product lands on an edge from below this often
+
+
+def test_mag_overlap_sub_intervals_floor_the_exact_product():
+    """50%-overlapping magnitude bins: the sub-interval floor(u * (n + 1)) of
+    the exact product, on the doubles around every sub-interval edge."""
+    for n_mag in (2, 3, 5, 9, 10, 19):
+        us = _adversarial_normalised([n_mag + 1])
+        m = np.array([0.0, 1.0] + us)
+        a, b = oracle.mag_bins_overlap(m, n_mag)
+        for k, u in enumerate(m):
+            want = _mag_bins_by_membership(Fraction(float(u)), n_mag)
+            got = [int(a[k])] + ([int(b[k])] if b[k] >= 0 else [])
+            assert got == want, (n_mag, float(u), got, want)
