@@ -119,6 +119,35 @@ int gce_search(const double *times, const double *mags,
                int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
                double *out_ce, gce_best_t *out_best, void *stream);
 
+/*
+ * gce_search_noalloc -- gce_search for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It calls no hipMalloc, hipFree or other allocating
+ * routine: the workspace lives in one device array of
+ * GCE_NOALLOC_SCRATCH_BYTES owned by the library, one per device, held
+ * from the library's first use of that device until the process ends.
+ *
+ * Arguments and results as for gce_search (FP64 bins, bit-exact with the
+ * documented arithmetic).  Curves are searched in their given order with the
+ * c ln c table in global memory.  The offsets are copied from HOST memory
+ * with hipMemcpyAsync on `stream`.  Every part of the array is written by a
+ * call before that call reads it, so nothing depends on an earlier call's
+ * contents.  All calls on one device share its array: calls that overlap on
+ * one device (on different streams, or from several threads) race on it.
+ *
+ * Returns GCE_EWORKSPACE, before touching the device, for shapes whose
+ * workspace exceeds the array (roughly: 40 bytes per work unit of 64
+ * periods x the heuristic Pdot trials per lane, plus 8 bytes per epoch,
+ * period and Pdot value); GCE_ENODEV without a gfx950 device; GCE_EHIP if a
+ * launch or the copy fails.
+ */
+#define GCE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gce_search_noalloc(const double *times, const double *mags,
+                       const int64_t *curve_offsets, int64_t n_curves,
+                       const double *periods, int64_t n_periods, const double *pdots,
+                       int64_t n_pdots, int32_t n_phase_bins, int32_t n_mag_bins,
+                       double *out_ce, gce_best_t *out_best, void *stream);
+
 /* --------------------------------------------------------------------------
  * Plans: validation, scheduling and allocation once; execution many times.
  * gce_plan_execute allocates nothing and copies nothing between host and

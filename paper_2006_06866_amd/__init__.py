@@ -78,6 +78,8 @@ def lib():
         L.gce_status_string.argtypes = [ctypes.c_int]
         L.gce_search.argtypes = [_vp, _vp, ctypes.POINTER(_i64), _i64, _vp, _i64, _vp,
                                  _i64, _i32, _i32, _vp, _vp, _vp]
+        L.gce_search_noalloc.argtypes = [_vp, _vp, ctypes.POINTER(_i64), _i64, _vp, _i64, _vp,
+                                         _i64, _i32, _i32, _vp, _vp, _vp]
         L.gce_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_i64), _i64,
                                       _i64, _i64, _i32, _i32, ctypes.POINTER(_Opts), _i32]
         L.gce_plan_execute.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -321,19 +323,35 @@ def merge_results(acc: Optional[np.ndarray], acc_trials: int, part, n_periods: i
 
 def search(times: torch.Tensor, mags: torch.Tensor, offsets, periods: torch.Tensor,
            pdots: torch.Tensor, n_phase: int, n_mag: int, want_cube: bool = True,
-           stream=None):
-    """One-call FP64 search through gce_search.  Returns (cube or None, best)."""
+           stream=None, out_ce: Optional[torch.Tensor] = None,
+           out_best: Optional[torch.Tensor] = None, no_alloc: bool = False):
+    """One-call FP64 search through gce_search, or gce_search_noalloc with
+    no_alloc=True (its workspace is the library's fixed device array; the
+    library allocates nothing).  out_ce / out_best may be given (else they are
+    allocated here, by torch).  Returns (cube or None, best)."""
     device = times.device
     for name, x in (("times", times), ("mags", mags), ("periods", periods),
                     ("pdots", pdots)):
         _dev_f64(x, name, device)
     off = _host_offsets(offsets)
     nc = off.size - 1
-    cube = (torch.empty((nc, pdots.numel(), periods.numel()), dtype=torch.float64,
-                        device=device) if want_cube else None)
-    best = torch.empty((nc, BEST_WORDS), dtype=torch.float64, device=device)
+    cube = out_ce
+    if cube is None and want_cube:
+        cube = torch.empty((nc, pdots.numel(), periods.numel()), dtype=torch.float64,
+                           device=device)
+    if cube is not None and (cube.dtype != torch.float64 or not cube.is_contiguous()
+                             or cube.numel() != nc * pdots.numel() * periods.numel()
+                             or cube.device != device):
+        raise ValueError("out_ce has the wrong dtype, size or device")
+    best = out_best
+    if best is None:
+        best = torch.empty((nc, BEST_WORDS), dtype=torch.float64, device=device)
+    elif (best.numel() != nc * BEST_WORDS or best.device != device
+          or best.element_size() != 8 or not best.is_contiguous()):
+        raise ValueError("out_best has the wrong size, element size, layout or device")
+    entry = lib().gce_search_noalloc if no_alloc else lib().gce_search
     with torch.cuda.device(device):
-        _check(lib().gce_search(_ptr(times), _ptr(mags),
+        _check(entry(_ptr(times), _ptr(mags),
                                 off.ctypes.data_as(ctypes.POINTER(_i64)), nc,
                                 _ptr(periods), periods.numel(), _ptr(pdots),
                                 pdots.numel(), int(n_phase), int(n_mag), _ptr(cube),

@@ -18,7 +18,8 @@ FILE_SEARCH = os.path.join(PKG, "gce_file_search")
 # the search-kernel variants are spread over four files so they compile in
 # parallel
 SOURCES = ["gce_kernels.hip", "gce_search_fp64.hip", "gce_search_fp64_overlap.hip",
-           "gce_search_split.hip", "gce_search_split_overlap.hip", "gce_api.cpp"]
+           "gce_search_split.hip", "gce_search_split_overlap.hip", "gce_noalloc.hip",
+           "gce_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

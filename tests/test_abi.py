@@ -190,3 +190,23 @@ def test_injected_allocation_failure(monkeypatch):
         with pytest.raises(gce.GceError) as ei:
             gce.Plan(off, 10, 2, 10, 5, device="cuda:0")
         assert ei.value.status == -5
+
+
+def test_noalloc_entry_point_bounds_its_workspace_on_host():
+    """gce_search_noalloc refuses shapes beyond its fixed device array with
+    GCE_EWORKSPACE and bad arguments with GCE_EINVAL, before any device call."""
+    _ensure_built()
+    L = gce.lib()
+    dummy = ctypes.c_void_p(16)   # never dereferenced: the calls fail first
+    off = np.arange(0, 513 * 600, 600, dtype=np.int64)   # 512 curves x 600 epochs
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = L.gce_search_noalloc(dummy, dummy, offp, 512, dummy, 20000, dummy, 64, 10, 5, None,
+                              dummy, None)
+    assert rc == -4
+    assert b"scratch" in L.gce_status_string(rc)
+    rc = L.gce_search_noalloc(dummy, dummy, offp, 512, dummy, 20000, dummy, 64, 129, 5, None,
+                              dummy, None)
+    assert rc == -1
+    rc = L.gce_search_noalloc(None, dummy, offp, 512, dummy, 100, dummy, 1, 10, 5, None,
+                              dummy, None)
+    assert rc == -1
