@@ -18,7 +18,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ce_oracle.c")
-_LIB = os.path.join(_HERE, "libce_oracle.so")
+# CE_ORACLE_LIB names another build of ce_oracle.c to load (the sanitizer
+# test builds one with AddressSanitizer and UndefinedBehaviorSanitizer)
+_LIB = os.environ.get("CE_ORACLE_LIB") or os.path.join(_HERE, "libce_oracle.so")
 
 # -ffp-contract=off: no fused multiply-adds other than the explicit fma().
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
