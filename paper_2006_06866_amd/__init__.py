@@ -24,7 +24,10 @@ __all__ = [
     "PRECISION_FP64", "PRECISION_SPLIT_FP32", "TABLE_AUTO", "TABLE_GLOBAL", "TABLE_LDS",
 ]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgce.so")
+# GCE_LIB names another build of the library to load (the host-sanitizer
+# test builds one); it must exist like the default one
+LIB_PATH = (os.environ.get("GCE_LIB")
+            or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgce.so"))
 
 PRECISION_FP64 = 0
 PRECISION_SPLIT_FP32 = 1
