@@ -4,11 +4,14 @@
 One step = one whole search (grid set-up, per-curve preparation, the search
 kernel writing the full CE cube, per-curve minimum) over the batched workload:
 512 synthetic light curves x 600 epochs, 20,000 periods x 64 Pdots, 10 phase x
-5 magnitude bins (Katz et al. 2020, Sec. 2.3).  `value` is the FP64 path
-(bit-exact bins); the split-precision path (FP32 Pdot term and binning) is
-timed the same way and compared with it: recovered minima, CE differences and
-bin mismatches.  Inputs are resident in HBM before each timed region.  Prints
-one JSON line.
+5 magnitude bins (Katz et al. 2020, Sec. 2.3).  The timed steps are replays of
+the whole search captured once in a HIP graph (--eager: launches instead).
+`value` is the FP64 path (bit-exact bins); the split-precision path (FP32 Pdot
+term and binning) is timed the same way and compared with it: recovered
+minima, CE differences and bin mismatches.  The ragged (8,192 curves) and
+long-baseline (64 x 5,000 epochs, 20 x 10 bins) workloads run the same two
+legs with fewer steps, under "workloads".  Inputs are resident in HBM before
+each timed region.  Prints one JSON line.
 """
 import argparse
 import json
@@ -45,18 +48,16 @@ WORKLOADS = {
 TABLES = {"auto": 0, "global": 1, "lds": 2}
 
 
-def flops_per_point_trial(precision, n_pd, n_phase, n_mag, mean_n, entries_per_point=1.0):
-    """Algorithmic flops per point-trial (FMA = 2), the precision's own kind.
-
-    FP64: per point and trial y = fma(-Pdot/2, x^2, x) (2), y - floor(y) (1),
-    phase * n_phase (1); per point and period, shared by the n_pd trials,
-    x = dt * (1/P) (1) and x^2 (1).  Split: the per-trial part in FP32, the
-    same 4 flops.  Both: per trial the entropy sums, n_phase * (n_mag + 1)
-    additions, a subtraction and a division, spread over the curve's points.
-    With overlapping magnitude bins the per-point part is done once per
-    histogram entry (entries_per_point per epoch).
-    """
-    return (4.0 + 2.0 / n_pd) * entries_per_point + (n_phase * (n_mag + 1) + 2) / mean_n
+# The defining expression of the fold and bin (Eq. (3), one point-trial):
+# x = dt * (1/P), x^2, y = fma(-Pdot/2, x^2, x), floor(y), y - floor(y),
+# phase * n_phase, conversion to an integer bin: 7 operations, 8 flops with
+# the fma counted as 2.  The kernels compute x and x^2 once per (epoch,
+# period) and reuse them along the Pdot axis, and fuse fract and the floored
+# product, so they issue fewer instructions than these counts: the 7-lane-op
+# rate can exceed the lane-op peak, and the flop rate is the fraction that
+# stays below 1.
+FLOPS_PER_POINT_TRIAL = 8.0
+LANE_OPS_PER_POINT_TRIAL = 7.0
 
 
 def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
@@ -70,7 +71,7 @@ def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
     FP32 fmas (Pdot term, rounding) at half a slot, fract and the address
     (3 slots).  Per epoch and lane, shared by the lane's tq Pdot trials:
     FP64 x and x^2 (2); split x and frac(x) in FP64, two conversions to
-    float, the half-bin shift and x^2 in FP32 (5).
+    float and x^2 in FP32 (4.5).
 
     Segment flush, per magnitude segment, phase bin and packed word (two
     trials): the marginal add, two table-offset extractions and two FP64
@@ -82,7 +83,7 @@ def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
     With overlapping magnitude bins an epoch is folded once per magnitude
     bin that holds it: the per-point part scales by the entries per epoch."""
     import numpy as np
-    point = (4.0 + 2.0 / tq if precision == 0 else 3.0 + 5.0 / tq) * entries_per_point
+    point = (4.0 + 2.0 / tq if precision == 0 else 3.0 + 4.5 / tq) * entries_per_point
     k = 5.0 + (1.0 if w.phase_overlap else 0.0)
     words = (tq + 1) // 2
     lengths = np.asarray(w.lengths, dtype=np.float64)
@@ -258,25 +259,49 @@ def measured_traffic(config, precision, as_recorded=True):
     return rec.get("per_launch_bytes", {}).get(key)
 
 
+def measured_counters(config, precision):
+    """Counter-measured VALU busy of the search kernel on this workload from
+    the committed rocprofv3 summary (SQ_INSTS_VALU x 4 cycles / (kernel
+    cycles x 1024 SIMDs), with the fraction of 2-cycle FP32 fmas counted at
+    half a slot), or None when the kernel source has changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_search_counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        sha = search_source_sha256()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    key = f"c{config}_{'fp64' if precision == 0 else 'split'}"
+    return rec.get("kernels", {}).get(key)
+
+
 def roofline(precision, w, kernel_s, config, tq, entries_per_point=1.0, as_recorded=True):
-    """entries_per_point: histogram entries per epoch (above 1 only with
-    overlapping magnitude bins, where an epoch is folded once per bin that
-    holds it)."""
+    """The dominant kernel (the search) against the VALU peak of its
+    precision.  `achieved` counts the defining expression's 8 flops per
+    point-trial (FMA = 2) over the workload's point-trials in one launch,
+    divided by the kernel's mean launch time.  entries_per_point: histogram
+    entries per epoch (above 1 only with overlapping magnitude bins, where an
+    epoch is folded once per bin that holds it)."""
     pt = w.point_trials
-    mean_n = float(w.lengths.mean())
-    fpp = flops_per_point_trial(precision, w.pdots.size, w.n_phase, w.n_mag,
-                                mean_n, entries_per_point)
-    achieved = fpp * pt / kernel_s / 1e12
+    rate = pt / kernel_s
+    achieved = FLOPS_PER_POINT_TRIAL * rate / 1e12
     peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
-    instr = valu_instr_per_point_trial(precision, tq, w, entries_per_point)
+    slots = valu_instr_per_point_trial(precision, tq, w, entries_per_point)
     return {
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak,
         "traffic": measured_traffic(config, precision, as_recorded),
         "kernel": "k_search<%s>" % ("fp64" if precision == 0 else "split"),
-        "kernel_ms": kernel_s * 1e3, "flops_per_point_trial": fpp,
-        "valu_instr_per_point_trial": instr,
-        "valu_frac": instr * pt / kernel_s / 1e12 / PEAK_VALU_TLANE,
+        "kernel_ms": kernel_s * 1e3,
+        "flops_per_point_trial": FLOPS_PER_POINT_TRIAL,
+        "lane_ops_per_point_trial": LANE_OPS_PER_POINT_TRIAL,
+        "frac_lane_ops": LANE_OPS_PER_POINT_TRIAL * rate / 1e12 / PEAK_VALU_TLANE,
+        "valu_slots_per_point_trial": slots,
+        "valu_frac_model": slots * rate / 1e12 / PEAK_VALU_TLANE,
+        "valu_busy_counters": measured_counters(config, precision) if as_recorded else None,
     }
 
 
@@ -329,6 +354,146 @@ def timing_sweep():
     return 0
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64, cube32, best64,
+                  best32):
+    """The split path's outputs against the FP64 path's, whose bins are
+    bit-exact to the oracle's (the GPU tests check that on every workload):
+    recovered minima, CE differences over the whole cube, bin mismatches on
+    4,096 sampled trials."""
+    bf64, bf32 = gce.best_fields(best64), gce.best_fields(best32)
+    strict = bf32["flat_index"] == bf64["flat_index"]
+    out = {"reference": "fp64 path (bins bit-exact to the oracle's)",
+           "best_equal_strict": f"{int(strict.sum())}/{w.n_curves}"}
+    if "inj_p" in w.truth:
+        found = (np.asarray(w.truth["inj_p"]) >= 0) & (
+            bf64["period_index"] == w.truth["inj_p"]) & (bf64["pdot_index"] == w.truth["inj_q"])
+        out["best_equal_strict_where_fp64_recovers_signal"] = (
+            f"{int(np.sum(strict & found))}/{int(found.sum())}")
+    if cube64 is not None and cube32 is not None:
+        flat64 = cube64.view(w.n_curves, -1)
+        h_at = flat64.gather(1, torch.from_numpy(bf32["flat_index"]).to(flat64.device)
+                             .view(-1, 1)).view(-1)
+        hmin = torch.from_numpy(bf64["ce_min"]).to(flat64.device)
+        out["best_equal_tolerant_1e-5"] = (
+            f"{int(((h_at - hmin) <= 1e-5).sum().item())}/{w.n_curves}")
+        flat32 = cube32.view(w.n_curves, -1)
+        mx, ok, n = 0.0, 0, 0
+        step = max(1, (1 << 28) // flat64.shape[1])
+        for c0 in range(0, w.n_curves, step):
+            dh = (flat32[c0:c0 + step].double() - flat64[c0:c0 + step]).abs()
+            mx = max(mx, float(dh.max().item()))
+            ok += int((dh <= 1e-5).sum().item())
+            n += dh.numel()
+            del dh
+        out["max_abs_dH"] = mx
+        out["frac_abs_dH_le_1e-5"] = ok / n
+    rng = np.random.default_rng(2006)
+    ci = rng.integers(0, w.n_curves, 4096)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, 4096)
+    c64 = plan64.debug_counts(*inputs, ci, fi).long()
+    c32 = plan32.debug_counts(*inputs, ci, fi).long()
+    moved = float((c64 - c32).abs().sum().item()) / 2
+    out["count_mismatch_rate"] = moved / float(w.lengths[ci].sum())
+    out["count_mismatch_sample"] = "4096 random trials"
+    return out
+
+
+def sample_trials(np, w, bf, n_curves_nb, n_random, seed):
+    """Trials to check against the oracle: each of n_curves_nb curves' minimum
+    and its +-2 neighbours in P and Pdot, plus n_random random trials."""
+    rng = np.random.default_rng(seed)
+    n_p, n_pd = w.periods.size, w.pdots.size
+    ci = list(rng.integers(0, w.n_curves, n_random))
+    fi = list(rng.integers(0, n_p * n_pd, n_random))
+    for c in rng.choice(w.n_curves, size=min(n_curves_nb, w.n_curves), replace=False):
+        if bf["flat_index"][c] < 0:
+            continue
+        q0, p0 = divmod(int(bf["flat_index"][c]), n_p)
+        for dq in range(-2, 3):
+            for dp in range(-2, 3):
+                if 0 <= q0 + dq < n_pd and 0 <= p0 + dp < n_p:
+                    ci.append(int(c))
+                    fi.append((q0 + dq) * n_p + p0 + dp)
+    return np.array(ci, dtype=np.int64), np.array(fi, dtype=np.int64)
+
+
+def gather(torch, np, cube, w, ci, fi):
+    q, p = np.divmod(fi, w.periods.size)
+    d = cube.device
+    idx = (torch.from_numpy(ci).to(d), torch.from_numpy(q).to(d), torch.from_numpy(p).to(d))
+    return cube[idx].double().cpu().numpy()
+
+
+def cpu_baseline_samples(np, w, ci, fi, g64, g32, bf64):
+    """Part of the cpu_baseline (oracle) leg: the oracle's CE at sampled trials against the
+    FP64 and split cubes there, and the FP64 minimum against every sampled
+    trial of its curve."""
+    import oracle
+    h = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase, w.n_mag,
+                      ci, fi, phase_overlap=w.phase_overlap, mag_overlap=w.mag_overlap)
+    d64 = np.abs(g64 - h)
+    beaten = int(np.sum(h < bf64["ce_min"][ci] - 1e-12))
+    out = {"trials": int(ci.size), "fp64_max_abs_dH": float(d64.max()),
+           "fp64_min_beaten_by_a_sample": beaten}
+    if g32 is not None:
+        d32 = np.abs(g32 - h)
+        out["split_max_abs_dH"] = float(d32.max())
+        out["split_frac_abs_dH_le_1e-5"] = float(np.mean(d32 <= 1e-5))
+    return out
+
+
+def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, tq,
+                 table, do_split, as_recorded):
+    """Both legs of one workload.  Returns (summary dict, FP64 leg state)."""
+    inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
+    pt = w.point_trials
+    plan64, cube64, best64, el64, k64 = timed_leg(
+        gce, torch, np, w, dev, inputs, 0, tq, steps, warmup, cube_on, graph, table)
+    log(f"c{config} fp64: {el64 / steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
+    entries = 1.0
+    if w.mag_overlap:
+        tot = plan64.debug_counts(*inputs, np.arange(w.n_curves),
+                                  np.zeros(w.n_curves, dtype=np.int64)).sum().item()
+        entries = float(tot) / float(w.offsets[-1]) / (2.0 if w.phase_overlap else 1.0)
+    res = {"value": pt * steps / el64, "unit": "point-trials/s",
+           "ms_per_step": el64 / steps * 1e3, "steps": steps, "warmup": warmup,
+           "trials_per_lane": plan64.info()["trials_per_lane"],
+           "table_in_lds": int(plan64.info()["table_in_lds"]),
+           "entries_per_epoch": entries,
+           "roofline": roofline(0, w, k64, config, plan64.info()["trials_per_lane"],
+                                entries, as_recorded)}
+    state = {"inputs": inputs, "plan64": plan64, "cube64": cube64, "best64": best64,
+             "cube32": None, "el64": el64}
+    if do_split:
+        plan32, cube32, best32, el32, k32 = timed_leg(
+            gce, torch, np, w, dev, inputs, 1, tq, steps, warmup, cube_on, graph, table)
+        log(f"c{config} split: {el32 / steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
+        split = {"value": pt * steps / el32, "unit": "point-trials/s",
+                 "ms_per_step": el32 / steps * 1e3, "speedup_vs_fp64": el64 / el32,
+                 "trials_per_lane": plan32.info()["trials_per_lane"],
+                 "table_in_lds": int(plan32.info()["table_in_lds"]),
+                 "roofline": roofline(1, w, k32, config, plan32.info()["trials_per_lane"],
+                                      entries, as_recorded)}
+        split.update(split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64,
+                                   cube32, best64, best32))
+        res["split"] = split
+        state["cube32"] = cube32
+        plan32.close()
+    return res, state
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,8 +513,13 @@ def main():
                          "and agreement with the single launch")
     ap.add_argument("--curves", type=int, default=0,
                     help="profiling aid: only the first CURVES curves of the workload")
-    ap.add_argument("--graph", action="store_true",
-                    help="time HIP-graph replays of the whole search")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager launches instead of HIP-graph replays")
+    ap.add_argument("--graph", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--extra", default="4,5",
+                    help="further workloads run after the headline one, with --extra-steps "
+                         "steps each ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU-baseline budget; 0 skips the oracle leg")
     ap.add_argument("--sweep", action="store_true",
@@ -387,42 +557,35 @@ def main():
     from paper_2006_06866_amd import synth
 
     dev = torch.device("cuda:0")
+    graph = not args.eager
     w = synth.make_config(args.config)
     if 0 < args.curves < w.n_curves:
         w = w.subset(range(args.curves))
     if args.mag_overlap:
         w.mag_overlap = True
     log(f"workload {WORKLOADS[args.config]}: {w.point_trials:.3g} point-trials")
-    inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
     pt = w.point_trials
     # the paper-scale cube would be 179 GB: minimum and statistics only
     cube_on = not args.no_cube and args.config != 6
-
-    plan64, cube64, best64, el64, k64 = timed_leg(
-        gce, torch, np, w, dev, inputs, 0, args.trials_per_lane, args.steps,
-        args.warmup, cube_on, args.graph, TABLES[args.table])
-    log(f"fp64: {el64 / args.steps * 1e3:.2f} ms/step, kernel {k64 * 1e3:.2f} ms")
-    # histogram entries per epoch: the total of one trial's histogram per
-    # curve (it does not depend on the trial)
-    entries = 1.0
-    if w.mag_overlap:
-        tot = plan64.debug_counts(*inputs, np.arange(w.n_curves),
-                                  np.zeros(w.n_curves, dtype=np.int64)).sum().item()
-        entries = float(tot) / float(w.offsets[-1]) / (2.0 if w.phase_overlap else 1.0)
-    # the committed traffic record is of the whole workload with default options
+    # the committed traffic and counter records are of the whole workload
+    # with default options
     as_recorded = (args.curves <= 0 and not args.no_cube and not args.mag_overlap
                    and args.table == "auto" and args.trials_per_lane == 0)
-    value = pt * args.steps / el64
+    head, st = run_workload(gce, torch, np, w, dev, args.config, args.steps, args.warmup,
+                            graph, cube_on, args.trials_per_lane, TABLES[args.table],
+                            not args.no_split, as_recorded)
+    plan64, cube64, best64, inputs = st["plan64"], st["cube64"], st["best64"], st["inputs"]
+    el64 = st["el64"]
     bf64 = gce.best_fields(best64)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "point-trials/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el64 / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -434,14 +597,13 @@ def main():
             "n_curves": w.n_curves, "points": int(w.offsets[-1]),
             "n_periods": int(w.periods.size), "n_pdots": int(w.pdots.size),
             "n_phase": w.n_phase, "n_mag": w.n_mag, "precision": "fp64",
-            "cube": cube_on, "trials_per_lane": plan64.info()["trials_per_lane"],
-            "table_in_lds": int(plan64.info()["table_in_lds"]),
-            "timing": "hip-graph replay" if args.graph else "eager launches",
+            "cube": cube_on, "trials_per_lane": head["trials_per_lane"],
+            "table_in_lds": head["table_in_lds"],
+            "timing": "hip-graph replay" if graph else "eager launches",
             "mag_overlap": bool(w.mag_overlap),
-            "entries_per_epoch": entries,
+            "entries_per_epoch": head["entries_per_epoch"],
         },
-        "roofline": roofline(0, w, k64, args.config, plan64.info()["trials_per_lane"],
-                             entries, as_recorded),
+        "roofline": head["roofline"],
     }
     if "p_true" in w.truth:
         # injections off the grid (Sec. 3.1 criterion), and the same search
@@ -495,57 +657,49 @@ def main():
         }
         log(f"chunked: {n_ranges} ranges, {el * 1e3:.1f} ms")
 
-    if not args.no_split:
-        plan32, cube32, best32, el32, k32 = timed_leg(
-            gce, torch, np, w, dev, inputs, 1, args.trials_per_lane, args.steps,
-            args.warmup, cube_on, args.graph, TABLES[args.table])
-        log(f"split: {el32 / args.steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
-        bf32 = gce.best_fields(best32)
-        strict = int(np.sum(bf32["flat_index"] == bf64["flat_index"]))
-        split = {
-            "value": pt * args.steps / el32, "unit": "point-trials/s",
-            "ms_per_step": el32 / args.steps * 1e3,
-            "speedup_vs_fp64": el64 / el32,
-            "trials_per_lane": plan32.info()["trials_per_lane"],
-            "table_in_lds": int(plan32.info()["table_in_lds"]),
-            "roofline": roofline(1, w, k32, args.config, plan32.info()["trials_per_lane"],
-                                 entries, as_recorded),
-            "best_equal_strict": f"{strict}/{w.n_curves}",
-        }
-        if cube_on:
-            # tolerant agreement: the FP64 CE at the split minimum is within
-            # 1e-5 of the FP64 minimum
-            flat64 = cube64.view(w.n_curves, -1)
-            h_at = flat64.gather(1, torch.from_numpy(bf32["flat_index"]).to(dev).view(-1, 1)).view(-1)
-            hmin = torch.from_numpy(bf64["ce_min"]).to(dev)
-            split["best_equal_tolerant_1e-5"] = (
-                f"{int(((h_at - hmin) <= 1e-5).sum().item())}/{w.n_curves}")
-            dh = (cube32.view(w.n_curves, -1).double() - flat64).abs()
-            split["max_abs_dH"] = float(dh.max().item())
-            split["frac_abs_dH_le_1e-5"] = float((dh <= 1e-5).double().mean().item())
-            del dh
-        # bin mismatches against the FP64 bins (which are bit-exact to the
-        # reference) on sampled trials
-        rng = np.random.default_rng(2006)
-        ci = rng.integers(0, w.n_curves, 4096)
-        fi = rng.integers(0, w.periods.size * w.pdots.size, 4096)
-        c64 = plan64.debug_counts(*inputs, ci, fi).long()
-        c32 = plan32.debug_counts(*inputs, ci, fi).long()
-        moved = float((c64 - c32).abs().sum().item()) / 2
-        split["count_mismatch_rate"] = moved / float(w.lengths[ci].sum())
-        split["count_mismatch_sample"] = "4096 random trials"
-        out["split"] = split
-        plan32.close()
-        del cube32
+    if "split" in head:
+        out["split"] = head["split"]
+    st["cube32"] = None
+    torch.cuda.empty_cache()
 
+    # oracle leg: the oracle timed on whole curves of the headline workload
+    # (compared with the FP64 cube rows), and kept for the samples of the
+    # further workloads below
     if args.cpu_seconds > 0:
         def rows(a, b):
             return None if cube64 is None else cube64[a:b].cpu().numpy()
         cb, par = cpu_baseline(w, rows, args.cpu_seconds)
+        cb["cpu_model"] = cpu_model()
         out["cpu_baseline"] = cb
         out["parity"] = par
-    print(json.dumps(out), flush=True)
     plan64.close()
+    del cube64, st
+    torch.cuda.empty_cache()
+
+    extras = [int(c) for c in args.extra.split(",") if c.strip()] if args.curves <= 0 else []
+    workloads = {}
+    for cfg in extras:
+        if cfg == args.config or cfg not in WORKLOADS or cfg == 6:
+            continue
+        we = synth.make_config(cfg)
+        log(f"workload {WORKLOADS[cfg]}: {we.point_trials:.3g} point-trials")
+        res, st = run_workload(gce, torch, np, we, dev, cfg, args.extra_steps, 1, graph,
+                               True, 0, 0, not args.no_split, True)
+        res["workload"] = WORKLOADS[cfg]
+        res["timing"] = "hip-graph replay" if graph else "eager launches"
+        bfe = gce.best_fields(st["best64"])
+        ci, fi = sample_trials(np, we, bfe, 16, 256, 300 + cfg)
+        g64 = gather(torch, np, st["cube64"], we, ci, fi)
+        g32 = gather(torch, np, st["cube32"], we, ci, fi) if st["cube32"] is not None else None
+        st["plan64"].close()
+        del st
+        torch.cuda.empty_cache()
+        if args.cpu_seconds > 0:
+            res["parity"] = cpu_baseline_samples(np, we, ci, fi, g64, g32, bfe)
+        workloads[f"c{cfg}"] = res
+    if workloads:
+        out["workloads"] = workloads
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -77,7 +77,13 @@ extern "C" {
 /* Precision of the fold / entropy arithmetic. */
 #define GCE_PRECISION_FP64 0        /* bit-exact bins, FP64 entropy */
 #define GCE_PRECISION_SPLIT_FP32 1  /* FP32 Pdot term and binning, FP64 entropy;
-                                       approximate bins, FP32 CE cube */
+                                       approximate bins, FP32 CE cube.  Its
+                                       phase is within E = 2^-22 + 2^-20 A
+                                       + 2^-52 x cycles of the FP64 phase
+                                       (x = (t - t0) / P, A = |Pdot| x^2 / 2;
+                                       E = 0 at x = 0), so an epoch's bin
+                                       differs from the FP64 bin only if its
+                                       FP64 phase lies within E of a bin edge */
 
 /* Per-curve result (48 bytes). */
 typedef struct {

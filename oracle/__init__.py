@@ -56,6 +56,8 @@ def _load():
         lib.ce_oracle_fold_bin.argtypes = [ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int32]
         lib.ce_oracle_fold_bin.restype = ctypes.c_int32
+        lib.ce_oracle_phases.argtypes = [_d, ctypes.c_int64, ctypes.c_double,
+                                         ctypes.c_double, _d]
         lib.ce_oracle_entropy.argtypes = [_u32, ctypes.c_int32, ctypes.c_int32]
         lib.ce_oracle_entropy.restype = ctypes.c_double
         lib.ce_oracle_counts.argtypes = [_d, _d, ctypes.c_int64, ctypes.c_double,
@@ -130,6 +132,17 @@ def fold_bin(dt: float, period: float, pdot: float, n_phase: int) -> int:
     """Phase bin of one epoch offset dt under Eq. (3)."""
     return int(_load().ce_oracle_fold_bin(float(dt), float(period), float(pdot),
                                           int(n_phase)))
+
+
+def phases(times, period: float, pdot: float) -> np.ndarray:
+    """Eq. (3) phases of one curve's epochs under one (P, Pdot) trial (time
+    origin: the curve's earliest epoch)."""
+    t = _f64(times)
+    out = np.empty(t.size)
+    rc = _load().ce_oracle_phases(_p(t, _d), t.size, float(period), float(pdot),
+                                  _p(out, _d))
+    _check(rc, "phases")
+    return out
 
 
 def entropy(counts) -> float:

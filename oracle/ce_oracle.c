@@ -149,14 +149,18 @@ static int32_t phase_bin(double phi, int32_t n_phase)
  * first and the Pdot term is applied with one fused multiply-add.
  * Returns the phase bin in [0, n_phase).
  * ------------------------------------------------------------------------- */
-static int32_t fold_bin(double dt, double inv_p, double half_pdot,
-                        int32_t n_phase)
+static double fold_phase(double dt, double inv_p, double half_pdot)
 {
     double x = dt * inv_p;
     double x2 = x * x;
     double y = fma(-half_pdot, x2, x);
-    double phi = y - floor(y);
-    return phase_bin(phi, n_phase);
+    return y - floor(y);
+}
+
+static int32_t fold_bin(double dt, double inv_p, double half_pdot,
+                        int32_t n_phase)
+{
+    return phase_bin(fold_phase(dt, inv_p, half_pdot), n_phase);
 }
 
 /* The classic P-only fold (Pdot absent): phi = frac(dt / P). */
@@ -165,6 +169,29 @@ static int32_t fold_bin_ponly(double dt, double inv_p, int32_t n_phase)
     double y = dt * inv_p;
     double phi = y - floor(y);
     return phase_bin(phi, n_phase);
+}
+
+/* ---------------------------------------------------------------------------
+ * Eq. (3) phases of one curve's n epochs under one (P, Pdot) trial, with the
+ * curve's earliest epoch as time origin: out_phi[k] in [0, 1) (a phase that
+ * rounds up to 1 is returned as 1.0 and binned into the last bin).
+ * Returns 0, ORACLE_EINVAL, or 1 if an epoch is not finite.
+ * ------------------------------------------------------------------------- */
+int ce_oracle_phases(const double *times, int64_t n, double period, double pdot,
+                     double *out_phi)
+{
+    if (n <= 0 || !times || !out_phi)
+        return ORACLE_EINVAL;
+    double t0 = times[0];
+    for (int64_t k = 0; k < n; ++k) {
+        if (!isfinite(times[k]))
+            return 1;
+        if (times[k] < t0) t0 = times[k];
+    }
+    double inv_p = 1.0 / period, half_pdot = 0.5 * pdot;
+    for (int64_t k = 0; k < n; ++k)
+        out_phi[k] = fold_phase(times[k] - t0, inv_p, half_pdot);
+    return ORACLE_OK;
 }
 
 /* Exposed for the exact-arithmetic fold tests. */

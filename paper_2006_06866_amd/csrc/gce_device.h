@@ -251,53 +251,56 @@ __device__ __forceinline__ void wave_argmin(double &h, int64_t &f)
 // ---------------------------------------------------------------------------
 // split-precision binning
 // ---------------------------------------------------------------------------
-// Split-precision bin.  FP64 forms x = dt / P and frac(x), FP32 the rest of
-// the point-period part (frac(x) - 1/(2n), the phase shifted down by half a
-// bin, and x^2 from x rounded to float); FP32 applies each
-// trial's Pdot term, reduces mod 1 and rounds n * phase to the nearest
-// integer by adding 1.5 * 2^23 (the float's low mantissa bits then hold the
-// integer).  round(n * frac(y - 1/(2n))) equals floor(n * frac(y)), except
-// that the upper half of bin 0 rounds to n: slot n is a wrap slot folded into
-// bin 0 at each flush.  The shift is 2^-23 cycle short of half a bin: a phase
-// exactly on a bin edge (every curve's first epoch has phase 0 for every
-// trial) would otherwise be an exact rounding tie decided by the float
-// rounding of 1/(2n); with the margin exact edges fall in the right bin, and
-// only phases within 2^-23 cycle below an edge move up (the float rounding
-// of the shift, at most 2^-29 cycle, keeps that margin for every n).
-// Accuracy is that of the FP32 Pdot term (~2e-7 of its size: x rounded to
-// float, squared, multiplied) and of frac(x) and the shift rounded to float
-// (2^-25 cycle each).
+// Split-precision bin.  FP64 forms x = dt / P and frac(x) (the step whose
+// magnitude needs it); FP32 converts frac(x) and x^2 to float, applies each
+// trial's Pdot term with one fma, reduces mod 1 (v_fract_f32, exact) and
+// floors n * phase by adding 1.5 * 2^23 in one fma: with the FP32 rounding
+// mode set toward minus infinity (split_round_down), the sum rounds to
+// 1.5 * 2^23 + floor(n * phase) of the exact product, and the float's low
+// mantissa bits hold that integer.  The phase is below 1, so the slot is in
+// [0, n).  Every FP32 instruction between split_round_down and
+// split_round_nearest rounds down: the conversions of frac(x) and x to float
+// and the Pdot fma err by under one ulp each (frac(x): 2^-24 cycle; the Pdot
+// term: about 3 * 2^-24 of its size), always in the same direction.
 constexpr float kRoundMagic = 12582912.0f;           // 1.5 * 2^23
 constexpr uint32_t kRoundMagicBits = 0x4B400000u;    // its bit pattern
 
-__device__ __forceinline__ double split_shift(int nph)
+// MODE register, FP_ROUND field bits 1:0 (FP32): 2 = toward -inf, 0 = nearest
+// even; the FP64 field (bits 3:2) is left alone.  The builtin (rather than
+// inline asm) tells the compiler that the write defines the mode register
+// that every FP32 instruction reads, so none is scheduled across it.  The
+// optimiser above that level still assumes the default rounding, so no FP32
+// value computed before split_round_down may be one that the binning also
+// computes (it could be reused): there is none.
+constexpr int kHwregModeFp32Round = 1 | (0 << 6) | ((2 - 1) << 11);   // hwreg(MODE, 0, 2)
+__device__ __forceinline__ void split_round_down()
 {
-    return 0.5 / (double)nph - 0x1p-23;
+    __builtin_amdgcn_s_setreg(kHwregModeFp32Round, 2);
+}
+__device__ __forceinline__ void split_round_nearest()
+{
+    __builtin_amdgcn_s_setreg(kHwregModeFp32Round, 0);
 }
 
 struct SplitPoint {
-    float xf;    // frac(x) - 1/(2n)
+    float xf;    // frac(x)
     float x2f;   // x^2
 };
 
-__device__ __forceinline__ SplitPoint split_point(double dt, double invp,
-                                                  double half_bin)
+__device__ __forceinline__ SplitPoint split_point(double dt, double invp)
 {
     const double x = dt * invp;
     SplitPoint sp;
-    // FP64 only where the magnitude of x demands it (x and its fraction);
-    // the half-bin shift and the square in FP32 (half-slot instructions),
-    // one slot per epoch fewer than both in FP64.  Measured on MI355X: split
-    // search 1.4% faster at 512 x 600 x 20,000 x 64, 3% at 50 x 10
-    // overlapping bins; bin mismatch against FP64 unchanged there (4.1e-7)
-    // and 1.37e-5 -> 1.46e-5 here.
-    sp.xf = (float)__builtin_amdgcn_fract(x) - (float)half_bin;
+    // FP64 only where the magnitude of x demands it (x and its fraction),
+    // the square in FP32 (a half-slot instruction)
+    sp.xf = (float)__builtin_amdgcn_fract(x);
     const float xs = (float)x;
     sp.x2f = xs * xs;
     return sp;
 }
 
-// Bit pattern kRoundMagicBits + slot, slot in [0, n] (n = wrap slot).
+// Bit pattern kRoundMagicBits + slot, slot = floor(n * phase) in [0, n),
+// under split_round_down.
 __device__ __forceinline__ uint32_t split_slot_bits(SplitPoint sp, float half_pdot,
                                                     float nph)
 {

@@ -274,7 +274,7 @@ size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max
 {
     const SearchVariant *v = find_variant(precision, 0, n_phase, tq, 0);
     const size_t regions = (size_t)(tq + 1) / 2;
-    const size_t slots = (size_t)n_phase + (precision == kPrecSplit ? 1 : 0);
+    const size_t slots = (size_t)n_phase;
     const size_t hist = regions * slots * kWave * sizeof(uint32_t);
     const size_t marg = regions * (size_t)n_phase * kWave * sizeof(uint32_t);
     size_t bytes = ((v && v->nph == 0) ? hist + marg : hist) * search_waves_per_block(lut_lds);
@@ -394,7 +394,6 @@ __global__ __launch_bounds__(64) void k_debug_counts(
     const int64_t q = f / dp.n_p, p = f % dp.n_p;
     const double invp = dp.inv_p[p], ha = dp.half_pd[q];
     const float ha32 = dp.half_pd32[q];
-    const double half_bin = split_shift(nph);
     const int64_t base = dp.mag_overlap ? 2 * dp.off[c] : dp.off[c];
     const int32_t *segc = dp.seg + c * (int64_t)(nmag + 1);
     for (int32_t j = 0; j < nmag; ++j) {
@@ -409,9 +408,14 @@ __global__ __launch_bounds__(64) void k_debug_counts(
                 fp64_phase_bins<1, 1>(xs, x2s, hpd, (double)nph, bb);
                 b = (int)bb[0];
             } else {
-                const SplitPoint sp = split_point(dt, invp, half_bin);
-                b = (int)(split_slot_bits(sp, ha32, (float)nph) - kRoundMagicBits);
-                if (b == nph) b = 0;   // wrap slot
+                split_round_down();
+                const SplitPoint sp = split_point(dt, invp);
+                const uint32_t bits = split_slot_bits(sp, ha32, (float)nph);
+                // the bin leaves through an asm operand before the mode is
+                // reset, so that its instructions all round down
+                asm volatile("" : : "v"(bits));
+                split_round_nearest();
+                b = (int)(bits - kRoundMagicBits);
             }
             // a slot outside [0, n_phase) is not counted, so that the row
             // totals show it

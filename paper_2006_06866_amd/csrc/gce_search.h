@@ -33,7 +33,6 @@ template <int PREC, int NPH, int TQ>
 struct SearchShape {
     static constexpr int kRegions = (TQ + 1) / 2;
     static constexpr bool kLdsMarg = (NPH == 0);
-    static constexpr int kWrap = (PREC == kPrecSplit) ? 1 : 0;   // extra slot
     // phase bins per scheduling group of the segment flush: about
     // GCE_FLUSH_WORDS words, i.e. twice that many table loads, in flight
     static constexpr int kFlushGroup =
@@ -63,7 +62,7 @@ void k_search(DevPlan dp, void *out_ce_v)
     // that everything derived from the work unit stays in scalar registers
     const int wave = WPB > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) : 0;
     const int nph = NPH > 0 ? NPH : dp.n_phase;
-    const int nslot = nph + S::kWrap;                   // LDS words per region
+    const int nslot = nph;                              // LDS words per region
     // LDS: [c ln c table (LL)] then one region per wave:
     // [R][nslot][64] histogram words, then [R][nph][64] marginals (NPH == 0)
     const size_t table_words = LL ? (size_t)2 * (dp.max_count + 1) : 0;
@@ -136,7 +135,6 @@ void k_search(DevPlan dp, void *out_ce_v)
 
     const double nphd = (double)nph;
     const float nphf = (float)nph;
-    const double half_bin = split_shift(nph);
     // split path: (bits << 8) of slot s is 0x40000000 + 256 s (mod 2^32)
     const uint32_t split_base = (uint32_t)lane * 4u - (kRoundMagicBits << 8);
     uniform_f64 *dts = (uniform_f64 *)(dp.dt_sorted + base);
@@ -172,7 +170,7 @@ void k_search(DevPlan dp, void *out_ce_v)
         } else {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const SplitPoint sp = split_point(dt[g], invp, half_bin);
+                const SplitPoint sp = split_point(dt[g], invp);
 #pragma unroll
                 for (int t = 0; t < TQ; ++t) {
                     const uint32_t bits = split_slot_bits(sp, ha32[t], nphf);
@@ -211,7 +209,7 @@ void k_search(DevPlan dp, void *out_ce_v)
     // spans disjoint bins b and b + 1 (mod n): its count is the sum of the
     // two words (packed halves cannot overflow: together they hold at most
     // the segment's entries, or twice that for a single phase bin, within
-    // the plan's count bound).  Bin 0's word (wrap slot merged) is kept in a
+    // the plan's count bound).  Bin 0's word is kept in a
     // register for the last bin, so every cell is cleared as soon as it is
     // read.
     // With the table in LDS (and NPH > 0) cells are never cleared.  They hold
@@ -223,8 +221,7 @@ void k_search(DevPlan dp, void *out_ce_v)
     // overlapping bins at N = 500, 3% slower on 10 x 5 bins at N = 600).
     constexpr bool kCum = NPH > 0 && LL;
     auto seg_word = [&](int r, int b) -> uint32_t {
-        uint32_t c = *cell(r, b);
-        if (S::kWrap && b == 0) c += *cell(r, nph);   // the wrap slot is bin 0's
+        const uint32_t c = *cell(r, b);
         const uint32_t w = c - vmarg[r][b];
         vmarg[r][b] = c;
         return w;
@@ -278,13 +275,7 @@ void k_search(DevPlan dp, void *out_ce_v)
         }
         uint32_t w0[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            w0[r] = *cell(r, 0);
-            if (S::kWrap) {   // the wrap slot belongs to bin 0
-                w0[r] += *cell(r, nph);
-                *cell(r, nph) = 0;
-            }
-        }
+        for (int r = 0; r < R; ++r) w0[r] = *cell(r, 0);
         if constexpr (NPH > 0) {
 #pragma unroll
             for (int b = 0; b < NPH; ++b) {
@@ -316,6 +307,9 @@ void k_search(DevPlan dp, void *out_ce_v)
         }
     };
 
+    // split path: FP32 rounds toward minus infinity while the epochs are
+    // binned (the bin fma floors n * phase), and to nearest again after
+    if constexpr (PREC == kPrecSplit) split_round_down();
     for (int32_t j = 0; j < dp.n_mag; ++j) {
         const int32_t k0 = segc[j], k1 = segc[j + 1];
         if (k0 == k1) continue;
@@ -354,6 +348,7 @@ void k_search(DevPlan dp, void *out_ce_v)
 
         flush_segment();
     }
+    if constexpr (PREC == kPrecSplit) split_round_nearest();
 
     double s2[TQ];
 #pragma unroll
@@ -364,12 +359,7 @@ void k_search(DevPlan dp, void *out_ce_v)
     };
     constexpr uint32_t nb_mask = OVL ? 0xffffffffu : 0u;
     if constexpr (NPH > 0) {
-        if constexpr (kCum) {
-            // the cells hold the marginal counts; fold the wrap slot into bin 0
-            if (S::kWrap)
-#pragma unroll
-                for (int r = 0; r < R; ++r) *cell(r, 0) += *cell(r, nph);
-        } else {
+        if constexpr (!kCum) {
             // the histograms are empty now: park the register marginals there
 #pragma unroll
             for (int b = 0; b < NPH; ++b)

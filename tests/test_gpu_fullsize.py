@@ -11,6 +11,7 @@ import oracle
 import paper_2006_06866_amd as gce
 from paper_2006_06866_amd import synth
 from gce_testlib import say, upload, ce_tolerance, check_counts_exact
+from split_band import argmin_gap_bound, check_counts_in_band
 
 pytestmark = pytest.mark.gpu
 
@@ -89,11 +90,17 @@ def test_fullsize_fp64_sampled(cfg):
     plan.close()
 
 
-@pytest.mark.parametrize("cfg", [2, 5])
+@pytest.mark.parametrize("cfg", [2, 4, 5])
 def test_fullsize_split_vs_fp64(cfg):
-    """Split path at full size: minima against the FP64 path's, and sampled
-    bins against the FP64 bins (bit-exact to the oracle)."""
+    """Split path at full size in the benchmark's launch configuration:
+    sampled bins against the oracle's within the error band
+    (tests/split_band.py), and minima against the FP64 path's (whose cube
+    is checked against the oracle above): identical for every curve whose
+    injected signal the FP64 search recovers; elsewhere the FP64 CE at the
+    split minimum is within 1e-5 of the FP64 minimum or within the gap the
+    band epochs of the two trials allow."""
     w = _workload(cfg)
+    say(f"[fullsize] split config {cfg}")
     t, m, P, Pd = upload(w)
     p64 = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
     p32 = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
@@ -103,17 +110,31 @@ def test_fullsize_split_vs_fp64(cfg):
     _, b32 = p32.execute(t, m, P, Pd)
     torch.cuda.synchronize()
     f64, f32 = gce.best_fields(b64), gce.best_fields(b32)
-    strict = np.mean(f64["flat_index"] == f32["flat_index"])
     at = cube64.view(w.n_curves, -1).gather(
         1, torch.from_numpy(f32["flat_index"]).cuda().view(-1, 1)).view(-1).cpu().numpy()
-    tolerant = np.mean(at - f64["ce_min"] <= 1e-5)
+    del cube64
+    tolerant = at - f64["ce_min"] <= 1e-5
+    has = w.truth["inj_p"] >= 0
+    found = has & (f64["period_index"] == w.truth["inj_p"]) & (
+        f64["pdot_index"] == w.truth["inj_q"])
+    strict = f64["flat_index"] == f32["flat_index"]
     rng = np.random.default_rng(7)
-    ci = rng.integers(0, w.n_curves, 2000)
-    fi = rng.integers(0, w.periods.size * w.pdots.size, 2000)
-    c64 = p64.debug_counts(t, m, P, Pd, ci, fi).long()
-    c32 = p32.debug_counts(t, m, P, Pd, ci, fi).long()
-    rate = float((c64 - c32).abs().sum().item()) / 2 / float(w.lengths[ci].sum())
-    say(f"[fullsize] split config {cfg}: best strict {strict:.4f} tolerant {tolerant:.4f} "
-        f"count mismatch {rate:.2e}")
-    assert tolerant >= 0.98
-    assert rate <= 1e-4
+    n_s = 2000 if cfg != 5 else 600
+    ci = rng.integers(0, w.n_curves, n_s)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, n_s)
+    c32 = p32.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy()
+    _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
+                            w.n_mag, ci, fi, want_counts=True)
+    band = check_counts_in_band(w, ci, fi, c32, want, label=f"config {cfg}")
+    say(f"[fullsize] split config {cfg}: best strict {strict.sum()}/{w.n_curves} "
+        f"(signal recovered by FP64: {found.sum()}, of them strict "
+        f"{np.sum(strict & found)}), tolerant {tolerant.sum()}; band {band}")
+    assert np.all(strict[found])
+    for c in np.flatnonzero(~tolerant):
+        gap = at[c] - f64["ce_min"][c]
+        bound = argmin_gap_bound(w, c, f32["flat_index"][c], f64["flat_index"][c])
+        say(f"[fullsize] curve {c}: FP64 CE at the split minimum {gap:.3e} above the "
+            f"FP64 minimum, band bound {bound:.3e}")
+        assert gap <= bound, (c, gap, bound)
+    p64.close()
+    p32.close()

@@ -4,8 +4,12 @@ Its bins approximate the FP64 reference, so the checks are:
   * self-consistency: every CE value equals Eq. (4) of the histogram the
     split binning produces (debug hook, same device bin code), to FP32
     output rounding;
-  * against the FP64 oracle: count-mismatch rate, |dH|, and the recovered
-    minimum (strictly equal, or within 1e-5 of the oracle's minimum CE).
+  * against the FP64 oracle, the error band (tests/split_band.py): a sampled
+    trial's histogram equals the oracle's unless one of its epochs has an
+    oracle phase within the split path's proven error bound of a bin edge,
+    and then differs by at most those epochs;
+  * the recovered minimum: identical to the oracle's for curves with a
+    signal, within 1e-5 of the oracle's minimum CE otherwise.
 Katz et al. 2020, Sec. 2.3, Eqs. (3)-(4).
 """
 import numpy as np
@@ -16,6 +20,7 @@ import oracle
 import paper_2006_06866_amd as gce
 from paper_2006_06866_amd import synth
 from gce_testlib import say, upload
+from split_band import check_counts_in_band
 
 pytestmark = pytest.mark.gpu
 
@@ -55,10 +60,8 @@ def test_split_self_consistent_and_close(n_phase, n_mag, tq):
     ci, fi, cnt = _self_consistency(plan, dev, w, gcube, 600, n_phase)
     _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, n_phase,
                             n_mag, ci, fi, want_counts=True)
-    moved = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2
-    rate = moved / w.lengths[ci].sum()
-    say(f"[split] count mismatch rate {rate:.2e}")
-    assert rate <= 1e-4
+    band = check_counts_in_band(w, ci, fi, cnt, want, label=f"nph={n_phase} tq={tq}")
+    say(f"[split] band {band}")
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
                                  n_phase, n_mag)
     # statistics over the split path's own (float) CE values
@@ -89,14 +92,20 @@ def test_split_overlap_self_consistent():
     assert np.all(np.abs(g[ci, q, p] - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12)
     _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, 10, 5, ci, fi,
                             want_counts=True, phase_overlap=True)
-    rate = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2 / (2 * w.lengths[ci].sum())
-    assert rate <= 1e-4
+    band = check_counts_in_band(w, ci, fi, cnt, want, phase_overlap=True, label="overlap")
+    say(f"[split] overlap band {band}")
 
 
 def test_split_lds_limit_is_reported():
-    # 128 phase bins plus the wrap slot and the marginals exceed 64 KiB of LDS
+    # 128 phase bins: one trial pair's histogram and marginals fill 64 KiB of
+    # LDS, as on the FP64 path; two pairs exceed it
+    plan = gce.Plan(np.array([0, 10]), 5, 1, 128, 5, precision=gce.PRECISION_SPLIT_FP32,
+                    trials_per_lane=1)
+    assert plan.info()["lds_bytes_per_wave"] == 64 * 1024
+    plan.close()
     with pytest.raises(gce.GceError) as ei:
-        gce.Plan(np.array([0, 10]), 5, 1, 128, 5, precision=gce.PRECISION_SPLIT_FP32)
+        gce.Plan(np.array([0, 10]), 5, 8, 128, 5, precision=gce.PRECISION_SPLIT_FP32,
+                 trials_per_lane=4)
     assert ei.value.status == -6
 
 
@@ -105,14 +114,20 @@ def test_split_c2_slice_agreement():
     w = synth.make_config(2).subset(np.arange(8))
     say("[split] c2 slice")
     plan, dev, gcube, bf = _split_run(w)
-    _self_consistency(plan, dev, w, gcube, 3000, 7)
+    ci, fi, cnt = _self_consistency(plan, dev, w, gcube, 3000, 7)
+    _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
+                            w.n_mag, ci, fi, want_counts=True)
+    band = check_counts_in_band(w, ci, fi, cnt, want, label="c2 slice")
     oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots,
                                  w.n_phase, w.n_mag)
     dh = np.abs(gcube.astype(np.float64) - oc)
-    frac_ok = np.mean(dh <= 1e-5)
-    say(f"[split] c2 slice: max|dH|={dh.max():.3e} frac(|dH|<=1e-5)={frac_ok:.6f} "
-        f"strict best {np.sum(bf['flat_index'] == obf)}/8")
-    assert frac_ok > 0.99
+    frac_bad = float(np.mean(dh > 1e-5))
+    say(f"[split] c2 slice: max|dH|={dh.max():.3e} frac(|dH|>1e-5)={frac_bad:.3e} "
+        f"band {band} strict best {np.sum(bf['flat_index'] == obf)}/8")
+    # a CE value moves only if an epoch of its trial lies in the band; the
+    # union bound over the sampled trials bounds how often that happens
+    assert frac_bad <= band["union_bound_mean"]
+    # every curve of this workload carries an eclipse signal: same minimum
     assert np.array_equal(bf["flat_index"], obf)
 
 
@@ -130,7 +145,7 @@ def test_split_random_shapes_self_consistent():
     """Seeded random shapes on the split path, every option drawn at once:
     each sampled CE value is Eq. (4) of the split path's own histogram (to
     float output rounding), histogram totals are the curve's entries, and the
-    bins agree with the FP64 oracle's but for a small fraction near edges."""
+    bins agree with the FP64 oracle's except for epochs in the error band."""
     rng = np.random.default_rng(6866)
     ran = 0
     for case in range(24):
@@ -168,8 +183,8 @@ def test_split_random_shapes_self_consistent():
         h_own = np.array([oracle.entropy(c) for c in cnt])
         q, p = np.divmod(fi, w.periods.size)
         assert np.all(np.abs(g[ci, q, p] - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12), label
-        moved = np.abs(cnt.astype(np.int64) - want.astype(np.int64)).sum() / 2
-        assert moved <= max(2.0, 1e-3 * want.sum()), (label, moved)
+        check_counts_in_band(w, ci, fi, cnt, want, phase_overlap=po, mag_overlap=mo,
+                             label=label)
         plan.close()
         ran += 1
     assert ran >= 15

@@ -85,6 +85,49 @@ def test_fold_matches_exact_rationals_on_dyadic_inputs():
         assert oracle.fold_bin(dt, P, Pd, n) == _exact_bin(dt, P, Pd, n)
 
 
+def _exact_phase(dt, period, pdot):
+    dt, P, Pd = Fraction(dt), Fraction(period), Fraction(pdot)
+    y = dt / P - Pd * dt * dt / (2 * P * P)
+    return y - math.floor(y)
+
+
+def test_phases_exact_on_dyadic_inputs():
+    """Eq. (3) phases: with dyadic epochs, P = 2^-k and Pdot = +-2^-m every
+    step of the fold is exact, so each phase equals the exact rational; the
+    time origin is the earliest epoch, whatever the epochs' order."""
+    rng = np.random.default_rng(15)
+    for _ in range(300):
+        t = rng.integers(0, 1 << 12, int(rng.integers(1, 20))).astype(np.float64) / 64.0
+        t += 1000.0                         # an origin that the fold must remove
+        P = 2.0 ** -int(rng.integers(2, 6))
+        Pd = float(rng.choice([0.0, 1.0, -1.0])) * 2.0 ** -int(rng.integers(9, 14))
+        phi = oracle.phases(t, P, Pd)
+        t0 = t.min()
+        for k in range(t.size):
+            assert Fraction(phi[k]) == _exact_phase(t[k] - t0, P, Pd)
+
+
+def test_phases_close_to_exact_and_binned_as_the_search():
+    """Generic inputs: each phase is within 1e-9 cycles of the exact phase
+    (rounding of x ~ 1e5 cycles), lies in [0, 1], and its bin
+    floor(phi * n) is the bin the oracle's histogram counts."""
+    rng = np.random.default_rng(16)
+    t = np.sort(rng.uniform(0.0, 3000.0, 40))
+    for _ in range(40):
+        P = rng.uniform(0.002, 0.05)
+        Pd = rng.choice([-1, 1]) * 10 ** rng.uniform(-13, -10)
+        phi = oracle.phases(t, P, Pd)
+        assert np.all((phi >= 0.0) & (phi <= 1.0))
+        for k in range(t.size):
+            ex = _exact_phase(t[k] - t[0], P, Pd)
+            d = abs(float(Fraction(phi[k]) - ex))
+            assert min(d, 1.0 - d) < 1e-9
+        mags = rng.uniform(0.0, 1.0, t.size)
+        cnt = oracle.counts(t, mags, P, Pd, 10, 1)
+        bins = np.array([min(math.floor(Fraction(v) * 10), 9) for v in phi])
+        assert np.array_equal(cnt[0], np.bincount(bins, minlength=10))
+
+
 def test_phase_bin_is_floor_of_exact_product():
     """Sec. 2.3 bins: phase phi lies in bin floor(phi * n) of the exact
     product.  Adversarial phases sit on and next to every bin edge k/n (the
