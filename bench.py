@@ -275,7 +275,13 @@ def measured_counters(config, precision):
     if rec.get("kernel_source_sha256") != sha:
         return None
     key = f"c{config}_{'fp64' if precision == 0 else 'split'}"
-    return rec.get("kernels", {}).get(key)
+    r = rec.get("kernels", {}).get(key)
+    if r is None:
+        return None
+    return {"valu_busy": r["valu_busy"], "waves_per_simd": r["waves_per_simd"],
+            "valu_instr_per_point_trial": r["valu_instr_per_point_trial"],
+            "lds_busy": r.get("lds_idx_active_per_cu_cycle"), "kernel": r["kernel"],
+            "workload": r["workload"], "record": "profiles/k_search_counters.json"}
 
 
 def roofline(precision, w, kernel_s, config, tq, entries_per_point=1.0, as_recorded=True):

@@ -512,6 +512,12 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         pl->split_unit = n_long * dp.units_per_curve;
     }
 
+    if ((dp.lut_lds || pl->split_unit > 0) &&
+        !gce::search_table_in_lds_ok(o.precision, dp.overlap, n_phase_bins, tq)) {
+        delete pl;
+        return fail(GCE_EUNSUPPORTED, "search kernel with the table in LDS has static LDS");
+    }
+
     // schedule: longest curves first (stable), so ragged batches drain evenly
     std::vector<int32_t> order((size_t)n_curves);
     std::iota(order.begin(), order.end(), 0);

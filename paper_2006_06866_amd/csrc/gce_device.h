@@ -32,6 +32,9 @@
 #ifndef GCE_SCALAR_EPOCHS
 #define GCE_SCALAR_EPOCHS 1     // read epoch offsets with scalar loads
 #endif
+#ifndef GCE_CUM_GROUP
+#define GCE_CUM_GROUP 12        // phase bins per group of the cumulative flush (one trial pair)
+#endif
 #ifndef GCE_WAVES_PER_EU
 #define GCE_WAVES_PER_EU 0      // occupancy hint for the search kernel (0: none)
 #endif
@@ -199,6 +202,27 @@ __device__ __forceinline__ void fp64_phase_bins(const double (&x)[G], const doub
         for (int t = 0; t < T; ++t)
             phi[g * T + t] = __builtin_amdgcn_fract(__builtin_fma(-half_pdot[t], x2[g], x[g]));
     fp64_floor_products<G * T>(phi, nph, bin);
+}
+
+// Sums of the low (high) 16-bit halves of two words in one instruction: an
+// SDWA add selecting the same half of both operands.
+__device__ __forceinline__ uint32_t add_low_halves(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD "
+        "src0_sel:WORD_0 src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ uint32_t add_high_halves(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD "
+        "src0_sel:WORD_1 src1_sel:WORD_1"
+        : "=v"(r)
+        : "v"(a), "v"(b));
+    return r;
 }
 
 __device__ __forceinline__ bool lex_less(double h1, int64_t f1, double h2,

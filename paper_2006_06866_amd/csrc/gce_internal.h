@@ -124,6 +124,11 @@ SearchTable search_table_split_overlap();
 
 // Search-kernel variants compiled into the library.
 bool search_variant_exists(int precision, int n_phase, int tq);
+// Whether the table-in-LDS variant of a shape can run (its kernel has no
+// static LDS, so the table it copies opens LDS at address 0).  Checked at
+// plan creation, which also keeps the answer for later launches (so a
+// captured launch makes no HIP query).
+bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq);
 // Waves per search block: the waves of a block share the LDS copy of the
 // c ln c table.
 constexpr int kLutWaves = 2;

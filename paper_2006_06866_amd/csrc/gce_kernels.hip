@@ -8,6 +8,9 @@
 //   k_search      the fold of Eq. (3), 2-D histogram, Eq. (4)        (hot loop,
 //                 gce_search.h, instantiated by gce_search_*.hip)
 //   k_epilogue    per-curve minimum over the work units              (argmin)
+#include <mutex>
+#include <unordered_map>
+
 #include "gce_device.h"
 
 namespace gce {
@@ -282,11 +285,35 @@ size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max
     return bytes;
 }
 
+// A variant with the c ln c table in LDS reads the table by LDS address,
+// taking the table to open the kernel's dynamic LDS at address 0; that holds
+// when the kernel has no static LDS, which is checked once per variant here.
+static bool table_at_lds_zero(const SearchVariant *v)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void *, bool> known;
+    const void *fn = reinterpret_cast<const void *>(v->fn);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = known.find(fn);
+    if (it != known.end()) return it->second;
+    hipFuncAttributes a;
+    const bool ok = hipFuncGetAttributes(&a, fn) == hipSuccess && a.sharedSizeBytes == 0;
+    known.emplace(fn, ok);
+    return ok;
+}
+
+bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq)
+{
+    const SearchVariant *v = find_variant(precision, overlap, n_phase, tq, 1);
+    return v && table_at_lds_zero(v);
+}
+
 hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
 {
     const SearchVariant *v =
         find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds);
     if (!v) return hipErrorInvalidValue;
+    if (v->ll && !table_at_lds_zero(v)) return hipErrorInvalidDeviceFunction;
     const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_count);
     const int wpb = search_waves_per_block(dp.lut_lds);
     const int64_t blocks = (dp.n_units - dp.unit0 + wpb - 1) / wpb;

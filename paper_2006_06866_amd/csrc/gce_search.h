@@ -39,7 +39,7 @@ struct SearchShape {
         kRegions >= GCE_FLUSH_WORDS ? 1 : GCE_FLUSH_WORDS / kRegions;
     // the same for the cumulative flush (table in LDS): 12 bins with one
     // trial pair (24 table loads), else as above (more cost registers)
-    static constexpr int kCumGroup = kRegions == 1 ? 12 : kFlushGroup;
+    static constexpr int kCumGroup = kRegions == 1 ? GCE_CUM_GROUP : kFlushGroup;
 };
 
 // LL = 1: the c ln c table is copied into LDS, shared by the block's
@@ -191,6 +191,23 @@ void k_search(DevPlan dp, void *out_ce_v)
         else
             return lut[w & 0xffffu];
     };
+    // the table entry at byte offset o (table in LDS: counts in units of 8).
+    // The FP64 kernels read the LDS copy through its LDS address, which is o
+    // itself: the table opens the kernel's dynamic LDS, which starts at LDS
+    // address 0 because the search kernels have no static LDS (the host
+    // checks that before launching a variant with the table in LDS).
+    // Addressing it off the array's symbol instead costs an add of that
+    // (link-time) address per table load.  Measured on 32 curves of the
+    // 50 x 10 overlapping-bin workload: FP64 search 896 -> 863 ms, split
+    // 867 -> 882 ms (same register count), so the split kernels keep the
+    // symbol-relative form.
+    auto lut_at = [&](uint32_t o) -> double {
+        if constexpr (LL && PREC == kPrecFp64)
+            return *reinterpret_cast<const __attribute__((address_space(3))) double *>(
+                static_cast<size_t>(o));
+        else
+            return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(lut) + o);
+    };
     auto lut_hi = [&](uint32_t w) -> double {
         if constexpr (LL)
             return *reinterpret_cast<const double *>(
@@ -255,9 +272,19 @@ void k_search(DevPlan dp, void *out_ce_v)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         if (b0 + i >= NPH) continue;
-                        const uint32_t w = OVL ? wv[i][r] + wv[i + 1][r] : wv[i][r];
-                        lo[i][r] = lut_lo(w);
-                        hi[i][r] = (2 * r + 1 < TQ) ? lut_hi(w) : 0.0;
+                        if constexpr (OVL && PREC == kPrecFp64) {
+                            // the two halves summed apart, one instruction
+                            // each: the low and high trial's table offsets
+                            const uint32_t a = wv[i][r], nb = wv[i + 1][r];
+                            lo[i][r] = lut_at(add_low_halves(a, nb));
+                            hi[i][r] = (2 * r + 1 < TQ) ? lut_at(add_high_halves(a, nb)) : 0.0;
+                        } else {
+                            // the packed sum (halves cannot carry: together
+                            // they hold at most the plan's count bound)
+                            const uint32_t w = OVL ? wv[i][r] + wv[i + 1][r] : wv[i][r];
+                            lo[i][r] = lut_lo(w);
+                            hi[i][r] = (2 * r + 1 < TQ) ? lut_hi(w) : 0.0;
+                        }
                     }
                 asm volatile("" ::: "memory");
 #pragma unroll
