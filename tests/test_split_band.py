@@ -3,6 +3,7 @@ binned from the oracle's phases moved by less than the error bound pass it,
 and so do moves only of epochs inside the band; a single epoch moved from
 outside the band fails it."""
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -96,3 +97,52 @@ def test_argmin_gap_bound_counts_band_epochs():
     t[1:4] = t[0] + np.array([1, 2, 3]) * w.periods[0] / w.n_phase
     w2 = synth.Workload(w.name, t, w.mags, w.offsets, w.periods, w.pdots, w.n_phase, w.n_mag)
     assert argmin_gap_bound(w2, 0, 0, 0) > base
+
+
+def _rd32(v):
+    """binary32 rounding toward minus infinity of an exact rational v."""
+    f = np.float32(float(v))            # round to nearest (via double)
+    if Fraction(float(f)) > v:
+        f = np.nextafter(f, np.float32(-np.inf))
+    # the double rounding above can land one float32 step low only when v
+    # lies exactly between; step back up while the next float32 is still <= v
+    while Fraction(float(np.nextafter(f, np.float32(np.inf)))) <= v:
+        f = np.nextafter(f, np.float32(np.inf))
+    return f
+
+
+def _split_phase(dt, period, pdot):
+    """The split path's phase, step by step as the kernel computes it: x and
+    frac(x) in binary64 (to nearest), then every binary32 operation rounded
+    toward minus infinity; Pdot/2 rounded to nearest float."""
+    invp = 1.0 / period
+    x = dt * invp
+    f = x - math.floor(x)
+    xf = _rd32(Fraction(f))
+    xs = _rd32(Fraction(x))
+    x2f = _rd32(Fraction(float(xs)) * Fraction(float(xs)))
+    ha = np.float32(0.5 * pdot)
+    y = _rd32(Fraction(float(xf)) - Fraction(float(ha)) * Fraction(float(x2f)))
+    return _rd32(Fraction(float(y)) - math.floor(float(y)))
+
+
+def test_error_bound_holds_for_the_split_arithmetic():
+    """The split phase (emulated exactly, rounding mode included) is within
+    E = phase_error_bound of the oracle's binary64 phase, mod 1, on random
+    trials whose Pdot term spans 0 to ~300 cycles, and on epochs at x = 0."""
+    rng = np.random.default_rng(23)
+    worst = 0.0
+    for i in range(3000):
+        period = 10 ** rng.uniform(-3.0, 0.0)
+        dt = 0.0 if i % 50 == 0 else rng.uniform(0.0, 3650.0)
+        pdot = rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(-14.0, -9.5)
+        phi64 = oracle.phases(np.array([0.0, dt]), period, pdot)[1]
+        ps = float(_split_phase(dt, period, pdot))
+        d = abs(ps - phi64)
+        d = min(d, 1.0 - d)
+        e = float(phase_error_bound(dt / period, 0.5 * pdot))
+        assert d < e or (e == 0.0 and d == 0.0), (dt, period, pdot, d, e)
+        if e > 0:
+            worst = max(worst, d / e)
+    # the bound is not vacuous: the largest error uses a fair part of it
+    assert 0.05 < worst < 1.0
