@@ -90,7 +90,7 @@ def test_fullsize_fp64_sampled(cfg):
     plan.close()
 
 
-@pytest.mark.parametrize("cfg", [2, 4, 5])
+@pytest.mark.parametrize("cfg", [2, 4, 5, 6])
 def test_fullsize_split_vs_fp64(cfg):
     """Split path at full size in the benchmark's launch configuration:
     sampled bins against the oracle's within the error band
@@ -98,13 +98,31 @@ def test_fullsize_split_vs_fp64(cfg):
     is checked against the oracle above): identical for every curve whose
     injected signal the FP64 search recovers; elsewhere the FP64 CE at the
     split minimum is within 1e-5 of the FP64 minimum or within the gap the
-    band epochs of the two trials allow."""
+    band epochs of the two trials allow.  Config 6 (the paper-scale grid,
+    no cube, overlapping phase bins): the sampled bins only."""
     w = _workload(cfg)
     say(f"[fullsize] split config {cfg}")
     t, m, P, Pd = upload(w)
-    p64 = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
+    po = w.phase_overlap
     p32 = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
-                   precision=gce.PRECISION_SPLIT_FP32)
+                   precision=gce.PRECISION_SPLIT_FP32, phase_overlap=po)
+    rng = np.random.default_rng(7)
+    n_s = {2: 2000, 4: 2000, 5: 600, 6: 800}[cfg]
+    ci = rng.integers(0, w.n_curves, n_s)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, n_s)
+    if cfg == 6:
+        _, b32 = p32.execute(t, m, P, Pd)
+        torch.cuda.synchronize()
+        c32 = p32.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy()
+        _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
+                                w.n_mag, ci, fi, want_counts=True, phase_overlap=po)
+        band = check_counts_in_band(w, ci, fi, c32, want, phase_overlap=po,
+                                    label=f"config {cfg}")
+        assert np.all(gce.best_fields(b32)["flat_index"] >= 0)
+        say(f"[fullsize] split config {cfg}: band {band}")
+        p32.close()
+        return
+    p64 = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
     cube64 = p64.new_cube()
     _, b64 = p64.execute(t, m, P, Pd, out_ce=cube64)
     _, b32 = p32.execute(t, m, P, Pd)
@@ -118,10 +136,6 @@ def test_fullsize_split_vs_fp64(cfg):
     found = has & (f64["period_index"] == w.truth["inj_p"]) & (
         f64["pdot_index"] == w.truth["inj_q"])
     strict = f64["flat_index"] == f32["flat_index"]
-    rng = np.random.default_rng(7)
-    n_s = 2000 if cfg != 5 else 600
-    ci = rng.integers(0, w.n_curves, n_s)
-    fi = rng.integers(0, w.periods.size * w.pdots.size, n_s)
     c32 = p32.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy()
     _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
                             w.n_mag, ci, fi, want_counts=True)
