@@ -278,9 +278,11 @@ def measured_counters(config, precision):
     r = rec.get("kernels", {}).get(key)
     if r is None:
         return None
+    kind = "fp64" if precision == 0 else "fp32"
     return {"valu_busy": r["valu_busy"], "waves_per_simd": r["waves_per_simd"],
             "valu_instr_per_point_trial": r["valu_instr_per_point_trial"],
-            "lds_busy": r.get("lds_idx_active_per_cu_cycle"), "kernel": r["kernel"],
+            "lds_busy": r.get("lds_idx_active_per_cu_cycle"),
+            "counted_tflops": r.get(f"counted_{kind}_tflops"), "kernel": r["kernel"],
             "workload": r["workload"], "record": "profiles/k_search_counters.json"}
 
 
