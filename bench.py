@@ -407,6 +407,18 @@ def split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64, cube32, bes
             del dh
         out["max_abs_dH"] = mx
         out["frac_abs_dH_le_1e-5"] = ok / n
+        # at the minima: the split CE at the FP64 minimum, and the split path's
+        # own minimum against the FP64 CE at that trial
+        f64i = torch.from_numpy(bf64["flat_index"]).to(flat64.device).view(-1, 1)
+        at64 = flat32.gather(1, f64i).view(-1).double() - hmin
+        at32 = torch.from_numpy(bf32["ce_min"]).to(flat64.device) - h_at
+        dmin = torch.maximum(at64.abs(), at32.abs()).cpu().numpy()
+        out["max_abs_dH_at_minima"] = float(dmin.max())
+        if "inj_p" in w.truth:
+            found = (np.asarray(w.truth["inj_p"]) >= 0) & (
+                bf64["period_index"] == w.truth["inj_p"]) & (bf64["pdot_index"] == w.truth["inj_q"])
+            if found.any():
+                out["max_abs_dH_at_minima_where_fp64_recovers_signal"] = float(dmin[found].max())
     rng = np.random.default_rng(2006)
     ci = rng.integers(0, w.n_curves, 4096)
     fi = rng.integers(0, w.periods.size * w.pdots.size, 4096)
