@@ -217,7 +217,7 @@ def _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph):
     return plan, cube, best, elapsed, float(np.mean(kernel_ms)) / 1e3
 
 
-SEARCH_SOURCES = ("gce_search.h", "gce_device.h")
+SEARCH_SOURCES = ("gce_search.h", "gce_search_co.h", "gce_device.h")
 
 
 def search_source_sha256(texts=None):
@@ -493,6 +493,7 @@ def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, 
            "ms_per_step": el64 / steps * 1e3, "steps": steps, "warmup": warmup,
            "trials_per_lane": plan64.info()["trials_per_lane"],
            "table_in_lds": int(plan64.info()["table_in_lds"]),
+           "waves_per_unit": plan64.info()["waves_per_unit"],
            "entries_per_epoch": entries,
            "roofline": roofline(0, w, k64, config, plan64.info()["trials_per_lane"],
                                 entries, as_recorded)}
@@ -506,6 +507,7 @@ def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, 
                  "ms_per_step": el32 / steps * 1e3, "speedup_vs_fp64": el64 / el32,
                  "trials_per_lane": plan32.info()["trials_per_lane"],
                  "table_in_lds": int(plan32.info()["table_in_lds"]),
+                 "waves_per_unit": plan32.info()["waves_per_unit"],
                  "roofline": roofline(1, w, k32, config, plan32.info()["trials_per_lane"],
                                       entries, as_recorded)}
         split.update(split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64,

@@ -192,6 +192,19 @@ typedef struct {
                                 table in LDS); with phase_overlap and
                                 n_phase_bins = 1 the limits halve again
                                 (GCE_EUNSUPPORTED beyond them). */
+    int32_t waves_per_unit;  /* waves that search one work unit (64 periods x
+                                trials_per_lane Pdot values of one curve):
+                                0 = automatic, 1, or 2 = two waves that split
+                                each magnitude bin's epochs and the phase bins
+                                of the entropy sums between them and add into
+                                one LDS copy of the unit's histograms (half
+                                the LDS per wave, so more waves per CU where
+                                histograms are large).  2 is compiled for 10
+                                and 20 phase bins at 4 and 8 (10) or 2, 4
+                                and 8 (20) trials per lane, and for 50 phase
+                                bins at 1, 2 and 4 (GCE_EUNSUPPORTED
+                                elsewhere); automatic takes 2 there when one
+                                wave's histograms would hold 8 KiB or more. */
 } gce_opts;
 
 #define GCE_TABLE_AUTO 0
@@ -271,8 +284,9 @@ typedef struct {
                                    over the curves of at most
                                    4 * n_phase * n_mag epochs (automatic
                                    placement of a ragged batch) */
-    int64_t work_units;         /* waves of one search launch */
+    int64_t work_units;         /* work units of one search launch */
     int64_t workspace_bytes;    /* device workspace held by the plan */
+    int32_t waves_per_unit;     /* waves that search one work unit: 1 or 2 */
 } gce_plan_info_t;
 
 /* Fill *info for the plan.  Returns GCE_EINVAL for NULL arguments. */
@@ -337,8 +351,9 @@ int gce_plan_destroy(gce_plan_t plan);
  * error of the calling thread's last failing call. */
 const char *gce_status_string(int status);
 
-/* Library version string ("gce-mi355x 0.2.0 (gfx950)"; 0.2.0 appended
- * mag_overlap to gce_opts and to gce_autotune's arguments). */
+/* Library version string ("gce-mi355x 0.3.0 (gfx950)"; 0.2.0 appended
+ * mag_overlap to gce_opts and to gce_autotune's arguments, 0.3.0 appended
+ * waves_per_unit to gce_opts and to gce_plan_info_t). */
 const char *gce_version(void);
 
 #ifdef __cplusplus

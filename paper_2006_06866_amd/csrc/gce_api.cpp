@@ -324,6 +324,7 @@ void gce::fill_shape(DevPlan &dp, int64_t n_curves, int64_t n_p, int64_t n_pd,
     dp.overlap = o.phase_overlap;
     dp.mag_overlap = o.mag_overlap;
     dp.lut_lds = lut_lds;
+    dp.co = 1;
 }
 
 gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_points)
@@ -385,6 +386,26 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 // Returns the number of curves of the first launch (the longest ones; the
 // schedule is longest first), or 0 for one launch; *short_max_count receives
 // the second launch's count bound (below the whole plan's, which passed).
+#ifndef GCE_CO_MIN_BYTES
+#define GCE_CO_MIN_BYTES 8192   // one-wave histogram bytes from which two waves share a unit
+#endif
+// Waves per work unit: two share one copy of the unit's histograms where a
+// wave's own copy would be large.  Measured on MI355X (kernel ms, one / two
+// waves per unit): 50 x 10 overlapping bins, 32 curves of the paper-scale
+// grid, 2 trials: 860 / 712; 20 x 10 bins, 64 x 5,000 epochs, 4 trials:
+// 1114 / 1057; split path, 10 x 5 bins, 8 trials: 46.1 / 44.6; but FP64,
+// 10 x 5 bins, 4 trials (5 KiB): 52.4 / 53.9.
+int heuristic_co(int precision, int n_phase, int tq, int lut_lds, int32_t max_count)
+{
+    const size_t hist = (size_t)((tq + 1) / 2) * n_phase * gce::kWave * sizeof(uint32_t);
+    return GCE_CO_MIN_BYTES > 0 && hist >= (size_t)GCE_CO_MIN_BYTES &&
+                   gce::search_variant_exists(precision, n_phase, tq, 2) &&
+                   gce::search_lds_bytes(precision, n_phase, tq, lut_lds, max_count, 2) <=
+                       gce::kMaxLdsBytes
+               ? 2
+               : 1;
+}
+
 int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase_overlap,
                         int mag_overlap, const int64_t *off, int64_t n_curves,
                         int32_t *short_max_count)
@@ -412,7 +433,7 @@ int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase
 
 extern "C" {
 
-const char *gce_version(void) { return "gce-mi355x 0.2.0 (gfx950)"; }
+const char *gce_version(void) { return "gce-mi355x 0.3.0 (gfx950)"; }
 
 const char *gce_status_string(int status)
 {
@@ -460,6 +481,8 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     if (o.table_placement != GCE_TABLE_AUTO && o.table_placement != GCE_TABLE_GLOBAL &&
         o.table_placement != GCE_TABLE_LDS)
         return fail(GCE_EINVAL, "table_placement must be 0, 1 or 2");
+    if (o.waves_per_unit != 0 && o.waves_per_unit != 1 && o.waves_per_unit != 2)
+        return fail(GCE_EINVAL, "waves_per_unit must be 0, 1 or 2");
     int32_t max_count = 0;
     rc = gce::count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
@@ -474,10 +497,16 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         return fail(GCE_EUNSUPPORTED,
                     "the table in LDS needs counts of at most 8191 (curves of at most "
                     "8191 epochs, half that with overlapping magnitude bins)");
-    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_count) >
+    const int co = o.waves_per_unit != 0
+                       ? o.waves_per_unit
+                       : heuristic_co(o.precision, n_phase_bins, tq, tl.lut_lds, max_count);
+    if (co == 2 && !gce::search_variant_exists(o.precision, n_phase_bins, tq, 2))
+        return fail(GCE_EUNSUPPORTED,
+                    "no two-wave search kernel for this phase-bin count and trials_per_lane");
+    if (gce::search_lds_bytes(o.precision, n_phase_bins, tq, tl.lut_lds, max_count, co) >
         gce::kMaxLdsBytes)
         return fail(GCE_EUNSUPPORTED,
-                    "a wave's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
+                    "a block's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
                     "table in global memory");
 
     DevPlan shape{};
@@ -503,6 +532,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
 
     DevPlan &dp = pl->dp;
     dp = shape;
+    dp.co = co;
     // whenever the placement is automatic and the batch keeps the table in
     // global memory (chosen by the heuristics or by tuning)
     if (o.table_placement == GCE_TABLE_AUTO && !tl.lut_lds) {
@@ -513,7 +543,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     }
 
     if ((dp.lut_lds || pl->split_unit > 0) &&
-        !gce::search_table_in_lds_ok(o.precision, dp.overlap, n_phase_bins, tq)) {
+        !gce::search_table_in_lds_ok(o.precision, dp.overlap, n_phase_bins, tq, dp.co)) {
         delete pl;
         return fail(GCE_EUNSUPPORTED, "search kernel with the table in LDS has static LDS");
     }
@@ -682,11 +712,12 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
     info->trials_per_lane = pl->dp.tq;
     info->lds_bytes_per_wave = (int32_t)(
         gce::search_lds_bytes(pl->dp.precision, pl->dp.n_phase, pl->dp.tq, pl->dp.lut_lds,
-                              pl->dp.max_count) /
-        gce::search_waves_per_block(pl->dp.lut_lds));
+                              pl->dp.max_count, pl->dp.co) /
+        gce::search_waves_per_block(pl->dp.lut_lds, pl->dp.co));
     info->table_in_lds = pl->split_unit > 0 ? 2 : pl->dp.lut_lds;
     info->work_units = pl->dp.n_units;
     info->workspace_bytes = (int64_t)pl->ws_bytes;
+    info->waves_per_unit = pl->dp.co;
     return GCE_OK;
 }
 

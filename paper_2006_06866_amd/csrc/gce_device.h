@@ -65,6 +65,13 @@ __device__ __forceinline__ uint32_t lds_add(uint32_t *p, uint32_t v)
                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// The same for a cell that the other waves of the block add into too.
+__device__ __forceinline__ uint32_t lds_add_block(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Eq. (3) phase bins in binary64, bit-identical to the documented sequence
 // y = fma(-Pdot/2, x^2, x); phi = y - floor(y); bin = floor(phi * n_phase),
 // the floor taken of the exact product.

@@ -3,7 +3,7 @@
 //
 //   gce_file_search DIR N_PHASE N_MAG [--split] [--phase-overlap]
 //                   [--mag-overlap] [--cube] [--table global|lds]
-//                   [--trials-per-lane T] [--device D]
+//                   [--trials-per-lane T] [--waves-per-unit W] [--device D]
 //
 // Reads, from DIR, little-endian raw arrays:
 //   times.f64, mags.f64   [sum N] epochs (days) and magnitudes, curve-major
@@ -32,7 +32,7 @@ int usage()
     std::fprintf(stderr,
                  "usage: gce_file_search DIR N_PHASE N_MAG [--split] [--phase-overlap] "
                  "[--mag-overlap] [--cube] [--table global|lds] [--trials-per-lane T] "
-                 "[--device D]\n");
+                 "[--waves-per-unit W] [--device D]\n");
     return 2;
 }
 
@@ -115,6 +115,7 @@ int main(int argc, char **argv)
             else if (v == "lds") opts.table_placement = GCE_TABLE_LDS;
             else return usage();
         } else if (a == "--trials-per-lane" && i + 1 < argc) opts.trials_per_lane = std::atoi(argv[++i]);
+        else if (a == "--waves-per-unit" && i + 1 < argc) opts.waves_per_unit = std::atoi(argv[++i]);
         else if (a == "--device" && i + 1 < argc) device = std::atoi(argv[++i]);
         else return usage();
     }

@@ -72,6 +72,8 @@ struct DevPlan {
     int32_t mag_overlap;      // 50%-overlapping magnitude bins: each curve's
                               // sorted-epoch region has room for 2N entries
     int32_t lut_lds;          // c ln c table copied into LDS by each wave
+    int32_t co;               // waves per work unit: 1, or 2 sharing one
+                              // copy of the unit's histograms
 
     // plan-time metadata
     const int64_t *off;       // [n_curves + 1] curve offsets
@@ -111,6 +113,7 @@ struct SearchVariant {
     int32_t nph;   // phase bins fixed at compile time; 0 = any count
     int32_t tq;    // Pdot trials per lane
     int32_t ll;    // c ln c table in LDS
+    int32_t co;    // waves per work unit (2: one histogram shared by both)
     SearchFn fn;
 };
 struct SearchTable {
@@ -123,19 +126,24 @@ SearchTable search_table_split();
 SearchTable search_table_split_overlap();
 
 // Search-kernel variants compiled into the library.
-bool search_variant_exists(int precision, int n_phase, int tq);
+bool search_variant_exists(int precision, int n_phase, int tq, int co = 1);
 // Whether the table-in-LDS variant of a shape can run (its kernel has no
 // static LDS, so the table it copies opens LDS at address 0).  Checked at
 // plan creation, which also keeps the answer for later launches (so a
 // captured launch makes no HIP query).
-bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq);
+bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq, int co = 1);
 // Waves per search block: the waves of a block share the LDS copy of the
-// c ln c table.
+// c ln c table; with two waves per work unit (co = 2) they also share the
+// unit's histograms.
 constexpr int kLutWaves = 2;
-inline int search_waves_per_block(int lut_lds) { return lut_lds ? kLutWaves : 1; }
+inline int search_waves_per_block(int lut_lds, int co = 1)
+{
+    return co == 2 ? 2 : lut_lds ? kLutWaves : 1;
+}
 // Bytes of LDS one search block uses (lut_lds: the c ln c table of
 // max_count + 1 entries is kept in LDS too, once per block).
-size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count);
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count,
+                        int co = 1);
 // Fill dp.order[rank] = rank (the identity schedule) on `s`.
 hipError_t launch_iota_order(const DevPlan &dp, hipStream_t s);
 

@@ -258,29 +258,37 @@ static SearchTable search_table(int precision, int overlap)
     return overlap ? search_table_split_overlap() : search_table_split();
 }
 
-static const SearchVariant *find_variant(int prec, int overlap, int n_phase, int tq, int ll)
+// Two-wave variants exist only for their own phase-bin count; one-wave
+// variants fall back on the runtime-count kernel.
+static const SearchVariant *find_variant(int prec, int overlap, int n_phase, int tq, int ll,
+                                         int co = 1)
 {
     const SearchTable t = search_table(prec, overlap);
     for (int32_t i = 0; i < t.n; ++i)
-        if (t.v[i].nph == n_phase && t.v[i].tq == tq && t.v[i].ll == ll) return &t.v[i];
+        if (t.v[i].nph == n_phase && t.v[i].tq == tq && t.v[i].ll == ll && t.v[i].co == co)
+            return &t.v[i];
+    if (co != 1) return nullptr;
     for (int32_t i = 0; i < t.n; ++i)
-        if (t.v[i].nph == 0 && t.v[i].tq == tq && t.v[i].ll == ll) return &t.v[i];
+        if (t.v[i].nph == 0 && t.v[i].tq == tq && t.v[i].ll == ll && t.v[i].co == 1)
+            return &t.v[i];
     return nullptr;
 }
 
-bool search_variant_exists(int precision, int n_phase, int tq)
+bool search_variant_exists(int precision, int n_phase, int tq, int co)
 {
-    return find_variant(precision, 0, n_phase, tq, 0) != nullptr;
+    return find_variant(precision, 0, n_phase, tq, 0, co) != nullptr;
 }
 
-size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count)
+size_t search_lds_bytes(int precision, int n_phase, int tq, int lut_lds, int max_count, int co)
 {
     const SearchVariant *v = find_variant(precision, 0, n_phase, tq, 0);
     const size_t regions = (size_t)(tq + 1) / 2;
     const size_t slots = (size_t)n_phase;
     const size_t hist = regions * slots * kWave * sizeof(uint32_t);
     const size_t marg = regions * (size_t)n_phase * kWave * sizeof(uint32_t);
-    size_t bytes = ((v && v->nph == 0) ? hist + marg : hist) * search_waves_per_block(lut_lds);
+    // two waves per unit keep one copy of the unit's histograms
+    size_t bytes = co == 2 ? hist
+                           : ((v && v->nph == 0) ? hist + marg : hist) * search_waves_per_block(lut_lds);
     if (lut_lds) bytes += sizeof(double) * (size_t)(max_count + 1);
     return bytes;
 }
@@ -302,21 +310,23 @@ static bool table_at_lds_zero(const SearchVariant *v)
     return ok;
 }
 
-bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq)
+bool search_table_in_lds_ok(int precision, int overlap, int n_phase, int tq, int co)
 {
-    const SearchVariant *v = find_variant(precision, overlap, n_phase, tq, 1);
+    const SearchVariant *v = find_variant(precision, overlap, n_phase, tq, 1, co);
     return v && table_at_lds_zero(v);
 }
 
 hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
 {
     const SearchVariant *v =
-        find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds);
+        find_variant(dp.precision, dp.overlap, dp.n_phase, dp.tq, dp.lut_lds, dp.co);
     if (!v) return hipErrorInvalidValue;
     if (v->ll && !table_at_lds_zero(v)) return hipErrorInvalidDeviceFunction;
-    const size_t lds = search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_count);
-    const int wpb = search_waves_per_block(dp.lut_lds);
-    const int64_t blocks = (dp.n_units - dp.unit0 + wpb - 1) / wpb;
+    const size_t lds =
+        search_lds_bytes(dp.precision, dp.n_phase, dp.tq, dp.lut_lds, dp.max_count, dp.co);
+    const int wpb = search_waves_per_block(dp.lut_lds, dp.co);
+    const int upb = dp.co == 2 ? 1 : wpb;   // work units per block
+    const int64_t blocks = (dp.n_units - dp.unit0 + upb - 1) / upb;
     const int64_t gx = blocks < kSearchGridX ? blocks : kSearchGridX;
     const int64_t gy = (blocks + gx - 1) / gx;
     hipLaunchKernelGGL(v->fn, dim3((unsigned)gx, (unsigned)gy), dim3(kWave * wpb), lds, s,

@@ -4,7 +4,8 @@
 // and phase-bin kind, so the variants compile in parallel.
 //
 // Search-kernel layout (one wave = one work unit; a block holds one wave, or
-// two sharing an LDS copy of the c ln c table):
+// two sharing an LDS copy of the c ln c table; k_search_co in
+// gce_search_co.h runs one unit on two waves instead):
 //   lane l          <-> period index p = 64 * tile + l
 //   trial t < TQ    <-> Pdot index q = TQ * group + t (same for the wave)
 //   epoch k         <-> uniform across the wave: dt_k is read with scalar
@@ -24,6 +25,7 @@
 #pragma once
 
 #include "gce_device.h"
+#include "gce_search_co.h"
 
 namespace gce {
 
@@ -463,16 +465,20 @@ void k_search(DevPlan dp, void *out_ce_v)
 // compiled phase-bin count (0 = any count), trials per lane and table
 // placement.  Expanded once in each gce_search_*.hip file.
 #define GCE_SV(P, O, N, T)                                                      \
-    SearchVariant{N, T, 0, &k_search<P, N, T, 0, O>},                           \
-        SearchVariant{N, T, 1, &k_search<P, N, T, 1, O>}
+    SearchVariant{N, T, 0, 1, &k_search<P, N, T, 0, O>},                        \
+        SearchVariant{N, T, 1, 1, &k_search<P, N, T, 1, O>}
+// the same shape also with two waves per work unit
+#define GCE_SV2(P, O, N, T)                                                     \
+    GCE_SV(P, O, N, T), SearchVariant{N, T, 0, 2, &k_search_co<P, N, T, 0, O>}, \
+        SearchVariant{N, T, 1, 2, &k_search_co<P, N, T, 1, O>}
 #define GCE_SEARCH_TABLE(P, O, FN)                                              \
     namespace gce {                                                             \
     static const SearchVariant kSearchTable[] = {                               \
-        GCE_SV(P, O, 10, 1), GCE_SV(P, O, 10, 2), GCE_SV(P, O, 10, 4),          \
-        GCE_SV(P, O, 10, 8), GCE_SV(P, O, 15, 1), GCE_SV(P, O, 15, 2),          \
+        GCE_SV(P, O, 10, 1), GCE_SV(P, O, 10, 2), GCE_SV2(P, O, 10, 4),         \
+        GCE_SV2(P, O, 10, 8), GCE_SV(P, O, 15, 1), GCE_SV(P, O, 15, 2),         \
         GCE_SV(P, O, 15, 4), GCE_SV(P, O, 15, 8), GCE_SV(P, O, 20, 1),          \
-        GCE_SV(P, O, 20, 2), GCE_SV(P, O, 20, 4), GCE_SV(P, O, 20, 8),          \
-        GCE_SV(P, O, 50, 1), GCE_SV(P, O, 50, 2), GCE_SV(P, O, 50, 4),          \
+        GCE_SV2(P, O, 20, 2), GCE_SV2(P, O, 20, 4), GCE_SV2(P, O, 20, 8),       \
+        GCE_SV2(P, O, 50, 1), GCE_SV2(P, O, 50, 2), GCE_SV2(P, O, 50, 4),       \
         GCE_SV(P, O, 0, 1),  GCE_SV(P, O, 0, 2),  GCE_SV(P, O, 0, 4),           \
         GCE_SV(P, O, 0, 8)};                                                    \
     SearchTable FN()                                                            \

@@ -37,12 +37,12 @@ def ce_tolerance(h_ref, n_phase, n_mag, n_points):
 
 
 def run_gpu(w, want_cube=True, trials_per_lane=0, stream=None, phase_overlap=False,
-            precision=0, table_placement=0, mag_overlap=False):
+            precision=0, table_placement=0, mag_overlap=False, waves_per_unit=0):
     t, m, P, Pd = upload(w)
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
                     trials_per_lane=trials_per_lane, phase_overlap=phase_overlap,
                     precision=precision, table_placement=table_placement,
-                    mag_overlap=mag_overlap)
+                    mag_overlap=mag_overlap, waves_per_unit=waves_per_unit)
     cube = plan.new_cube() if want_cube else None
     cube, best = plan.execute(t, m, P, Pd, out_ce=cube, stream=stream)
     torch.cuda.synchronize()

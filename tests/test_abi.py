@@ -130,6 +130,23 @@ def test_overlap_count_limits_rejected_on_host():
         assert rc == -1
 
 
+def test_waves_per_unit_checked_on_host():
+    """waves_per_unit is 0, 1 or 2 (else GCE_EINVAL); 2 needs a compiled
+    two-wave kernel for the phase-bin count and trials per lane (else
+    GCE_EUNSUPPORTED).  Both are refused before any device call."""
+    _ensure_built()
+    off = np.array([0, 5, 9])
+    for bad in (-1, 3):
+        with pytest.raises(gce.GceError) as ei:
+            gce.Plan(off, 10, 8, 10, 5, waves_per_unit=bad, device="cuda:0")
+        assert ei.value.status == -1, bad
+    for n_phase, tq in ((15, 4), (10, 1), (10, 2), (33, 2), (20, 1)):
+        with pytest.raises(gce.GceError) as ei:
+            gce.Plan(off, 10, 8, n_phase, 5, trials_per_lane=tq, waves_per_unit=2,
+                     device="cuda:0")
+        assert ei.value.status == -6, (n_phase, tq)
+
+
 def _write_inputs(d, w):
     w.times.astype("<f8").tofile(os.path.join(d, "times.f64"))
     w.mags.astype("<f8").tofile(os.path.join(d, "mags.f64"))

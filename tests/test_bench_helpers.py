@@ -46,7 +46,7 @@ def test_records_count_only_for_the_profiled_code():
         with open(os.path.join(ROOT, "paper_2006_06866_amd", "csrc", name)) as f:
             texts.append(f.read())
     assert bench.search_source_sha256([t + "\n// a note\n\n" for t in texts]) == sha
-    assert bench.search_source_sha256([texts[0] + "\nint x;\n", texts[1]]) != sha
+    assert bench.search_source_sha256([texts[0] + "\nint x;\n", *texts[1:]]) != sha
     if rec["kernel_source_sha256"] == sha:
         c = bench.measured_counters(2, 0)
         assert c is not None and 0.0 < c["valu_busy"] <= 1.05
