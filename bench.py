@@ -239,11 +239,21 @@ def search_source_sha256(texts=None):
     return h.hexdigest()
 
 
-def measured_traffic(config, precision, as_recorded=True):
+def search_kernel_name(precision, n_phase, phase_overlap, info):
+    """The search kernel a plan launches (its first launch, where a ragged
+    batch is searched in two), as rocprofv3 names it."""
+    nph = n_phase if n_phase in (10, 15, 20, 50) else 0
+    base = "gce::k_search_co" if info["waves_per_unit"] == 2 else "gce::k_search"
+    ll = 1 if info["table_in_lds"] == 1 else 0
+    return (f"{base}<{precision}, {nph}, {info['trials_per_lane']}, {ll}, "
+            f"{int(bool(phase_overlap))}>")
+
+
+def measured_traffic(config, kernel, as_recorded=True):
     """HBM bytes per search launch from the committed rocprofv3 counter
-    summary, or None when the kernel source has changed since it was taken
-    or the run differs from the recorded one (as_recorded: the whole
-    workload, default options)."""
+    summary, or None when the kernel source has changed since it was taken,
+    the run launches another kernel, or the run differs from the recorded
+    one (as_recorded: the whole workload, default options)."""
     if not as_recorded:
         return None
     path = os.path.join(ROOT, "profiles", f"k_search_c{config}_traffic.json")
@@ -255,16 +265,15 @@ def measured_traffic(config, precision, as_recorded=True):
         return None
     if rec.get("kernel_source_sha256") != sha:
         return None
-    key = "k_search<fp64>" if precision == 0 else "k_search<split>"
-    return rec.get("per_launch_bytes", {}).get(key)
+    return rec.get("per_launch_bytes", {}).get(kernel)
 
 
-def measured_counters(config, precision):
+def measured_counters(config, precision, kernel):
     """Counter-measured VALU busy of the search kernel on this workload from
     the committed rocprofv3 summary (SQ_INSTS_VALU x 4 cycles / (kernel
     cycles x 1024 SIMDs), with the fraction of 2-cycle FP32 fmas counted at
     half a slot), or None when the kernel source has changed since the
-    counters were taken."""
+    counters were taken or the run launches another kernel."""
     path = os.path.join(ROOT, "profiles", "k_search_counters.json")
     try:
         with open(path) as f:
@@ -276,7 +285,7 @@ def measured_counters(config, precision):
         return None
     key = f"c{config}_{'fp64' if precision == 0 else 'split'}"
     r = rec.get("kernels", {}).get(key)
-    if r is None:
+    if r is None or r["kernel"] != kernel:
         return None
     kind = "fp64" if precision == 0 else "fp32"
     return {"valu_busy": r["valu_busy"], "waves_per_simd": r["waves_per_simd"],
@@ -286,7 +295,7 @@ def measured_counters(config, precision):
             "workload": r["workload"], "record": "profiles/k_search_counters.json"}
 
 
-def roofline(precision, w, kernel_s, config, tq, entries_per_point=1.0, as_recorded=True):
+def roofline(precision, w, kernel_s, config, info, entries_per_point=1.0, as_recorded=True):
     """The dominant kernel (the search) against the VALU peak of its
     precision.  `achieved` counts the defining expression's 8 flops per
     point-trial (FMA = 2) over the workload's point-trials in one launch,
@@ -297,19 +306,21 @@ def roofline(precision, w, kernel_s, config, tq, entries_per_point=1.0, as_recor
     rate = pt / kernel_s
     achieved = FLOPS_PER_POINT_TRIAL * rate / 1e12
     peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
-    slots = valu_instr_per_point_trial(precision, tq, w, entries_per_point)
+    slots = valu_instr_per_point_trial(precision, info["trials_per_lane"], w, entries_per_point)
+    kernel = search_kernel_name(precision, w.n_phase, w.phase_overlap, info)
     return {
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": measured_traffic(config, precision, as_recorded),
-        "kernel": "k_search<%s>" % ("fp64" if precision == 0 else "split"),
+        "traffic": measured_traffic(config, kernel, as_recorded),
+        "kernel": kernel,
         "kernel_ms": kernel_s * 1e3,
         "flops_per_point_trial": FLOPS_PER_POINT_TRIAL,
         "lane_ops_per_point_trial": LANE_OPS_PER_POINT_TRIAL,
         "frac_lane_ops": LANE_OPS_PER_POINT_TRIAL * rate / 1e12 / PEAK_VALU_TLANE,
         "valu_slots_per_point_trial": slots,
         "valu_frac_model": slots * rate / 1e12 / PEAK_VALU_TLANE,
-        "valu_busy_counters": measured_counters(config, precision) if as_recorded else None,
+        "valu_busy_counters": (measured_counters(config, precision, kernel)
+                               if as_recorded else None),
     }
 
 
@@ -495,8 +506,7 @@ def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, 
            "table_in_lds": int(plan64.info()["table_in_lds"]),
            "waves_per_unit": plan64.info()["waves_per_unit"],
            "entries_per_epoch": entries,
-           "roofline": roofline(0, w, k64, config, plan64.info()["trials_per_lane"],
-                                entries, as_recorded)}
+           "roofline": roofline(0, w, k64, config, plan64.info(), entries, as_recorded)}
     state = {"inputs": inputs, "plan64": plan64, "cube64": cube64, "best64": best64,
              "cube32": None, "el64": el64}
     if do_split:
@@ -508,8 +518,8 @@ def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, 
                  "trials_per_lane": plan32.info()["trials_per_lane"],
                  "table_in_lds": int(plan32.info()["table_in_lds"]),
                  "waves_per_unit": plan32.info()["waves_per_unit"],
-                 "roofline": roofline(1, w, k32, config, plan32.info()["trials_per_lane"],
-                                      entries, as_recorded)}
+                 "roofline": roofline(1, w, k32, config, plan32.info(), entries,
+                                      as_recorded)}
         split.update(split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64,
                                    cube32, best64, best32))
         res["split"] = split

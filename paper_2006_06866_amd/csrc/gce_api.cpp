@@ -163,18 +163,49 @@ int heuristic_lut_lds(int precision, int n_phase, int n_mag, int tq, int32_t max
 
 int gce::set_error(int code, const char *msg) { return fail(code, msg); }
 
-int gce::heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count)
+#ifndef GCE_CO_MIN_BYTES
+#define GCE_CO_MIN_BYTES 8192   // one-wave histogram bytes from which two waves share a unit
+#endif
+// Waves per work unit: two share one copy of the unit's histograms where a
+// wave's own copy would be large.  Measured on MI355X (kernel ms, one / two
+// waves per unit): 50 x 10 overlapping bins, 32 curves of the paper-scale
+// grid, 2 trials: 860 / 712; 20 x 10 bins, 64 x 5,000 epochs, 4 trials:
+// 1114 / 1057; split path, 10 x 5 bins, 8 trials: 46.1 / 44.6; but FP64,
+// 10 x 5 bins, 4 trials (5 KiB): 52.4 / 53.9.
+int gce::heuristic_co(int precision, int n_phase, int tq, int lut_lds, int32_t max_count)
+{
+    const size_t hist = (size_t)((tq + 1) / 2) * n_phase * gce::kWave * sizeof(uint32_t);
+    return GCE_CO_MIN_BYTES > 0 && hist >= (size_t)GCE_CO_MIN_BYTES &&
+                   gce::search_variant_exists(precision, n_phase, tq, 2) &&
+                   gce::search_lds_bytes(precision, n_phase, tq, lut_lds, max_count, 2) <=
+                       gce::kMaxLdsBytes
+               ? 2
+               : 1;
+}
+
+int gce::heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count,
+                      int waves_per_unit)
 {
     // Pdot trials per lane: more trials share each epoch's x and x^2, but
     // every trial pair adds a histogram region of LDS and registers.
-    // Measured on MI355X (kernel ms at 1 / 2 / 4 / 8 trials):
+    // Measured on MI355X (kernel ms at 1 / 2 / 4 / 8 trials, one wave per
+    // work unit):
     //   FP64, 10 x 5 bins, 512 x 600 x 20,000 x 64:     - / 59.4 / 53.1 / 54.4
     //   FP64, 20 x 10 bins, 64 x 5,000 x 100,000 x 256: - / 1165 / 1121 / 1563
     //   split, 10 x 5 bins, 512 x 600 x 20,000 x 64:    - / 63.6 / 50.9 / 48.3
     //   split, 20 x 10 bins, 64 x 5,000 x ...:          - / 1213 / 1022 / 1539
     // so FP64 starts from 4 and the split path from 8, and a wave's
     // histograms stay within ~13 KiB (at 20 KiB the CU holds too few waves).
+    // With two waves per unit, FP64 at 10 x 5 bins and 8 trials keeps 5 KiB
+    // per wave, as 4 trials on one wave do, and was faster: 52.6 against
+    // 53.8 ms (one box); at 20 x 10 bins (10 KiB per wave) it was not, 1072
+    // against 1062 ms.  So FP64 starts from 8 where two waves hold eight
+    // trials in at most 5 KiB per wave.
     int tq = precision == GCE_PRECISION_FP64 ? 4 : 8;
+    const size_t hist8 = (size_t)4 * n_phase * kWave * sizeof(uint32_t);
+    if (precision == GCE_PRECISION_FP64 && waves_per_unit != 1 && hist8 / 2 <= 5 * 1024 &&
+        heuristic_co(precision, n_phase, 8, 0, max_count) == 2)
+        tq = 8;
     while (tq > 1 &&
            (tq >= 2 * n_pd || !gce::search_variant_exists(precision, n_phase, tq) ||
             gce::search_lds_bytes(precision, n_phase, tq, 0, max_count) > 13 * 1024))
@@ -198,7 +229,7 @@ namespace {
 // request and the heuristics for what was left open.
 Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t n_pd,
                      const int64_t *off, int64_t n_curves, int32_t max_count,
-                     int requested_tq, int requested_placement)
+                     int requested_tq, int requested_placement, int requested_co)
 {
     if (requested_tq == 0 && requested_placement == GCE_TABLE_AUTO) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -210,7 +241,9 @@ Tiling choose_tiling(int precision, int overlap, int n_phase, int n_mag, int64_t
             return it->second;
     }
     Tiling t{0, 0};
-    t.tq = requested_tq > 0 ? requested_tq : gce::heuristic_tq(precision, n_phase, n_pd, max_count);
+    t.tq = requested_tq > 0 ? requested_tq
+                            : gce::heuristic_tq(precision, n_phase, n_pd, max_count,
+                                                requested_co);
     if (requested_placement == GCE_TABLE_GLOBAL) t.lut_lds = 0;
     else if (requested_placement == GCE_TABLE_LDS) t.lut_lds = 1;
     else t.lut_lds = heuristic_lut_lds(precision, n_phase, n_mag, t.tq, max_count,
@@ -386,26 +419,6 @@ int overlap_bits(int32_t phase_overlap, int32_t mag_overlap)
 // Returns the number of curves of the first launch (the longest ones; the
 // schedule is longest first), or 0 for one launch; *short_max_count receives
 // the second launch's count bound (below the whole plan's, which passed).
-#ifndef GCE_CO_MIN_BYTES
-#define GCE_CO_MIN_BYTES 8192   // one-wave histogram bytes from which two waves share a unit
-#endif
-// Waves per work unit: two share one copy of the unit's histograms where a
-// wave's own copy would be large.  Measured on MI355X (kernel ms, one / two
-// waves per unit): 50 x 10 overlapping bins, 32 curves of the paper-scale
-// grid, 2 trials: 860 / 712; 20 x 10 bins, 64 x 5,000 epochs, 4 trials:
-// 1114 / 1057; split path, 10 x 5 bins, 8 trials: 46.1 / 44.6; but FP64,
-// 10 x 5 bins, 4 trials (5 KiB): 52.4 / 53.9.
-int heuristic_co(int precision, int n_phase, int tq, int lut_lds, int32_t max_count)
-{
-    const size_t hist = (size_t)((tq + 1) / 2) * n_phase * gce::kWave * sizeof(uint32_t);
-    return GCE_CO_MIN_BYTES > 0 && hist >= (size_t)GCE_CO_MIN_BYTES &&
-                   gce::search_variant_exists(precision, n_phase, tq, 2) &&
-                   gce::search_lds_bytes(precision, n_phase, tq, lut_lds, max_count, 2) <=
-                       gce::kMaxLdsBytes
-               ? 2
-               : 1;
-}
-
 int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase_overlap,
                         int mag_overlap, const int64_t *off, int64_t n_curves,
                         int32_t *short_max_count)
@@ -489,7 +502,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
     const Tiling tl = choose_tiling(o.precision, overlap_bits(o.phase_overlap, o.mag_overlap),
                                     n_phase_bins, n_mag_bins, n_pdots, curve_offsets,
                                     n_curves, max_count, o.trials_per_lane,
-                                    o.table_placement);
+                                    o.table_placement, o.waves_per_unit);
     const int tq = tl.tq;
     if (!gce::search_variant_exists(o.precision, n_phase_bins, tq))
         return fail(GCE_EUNSUPPORTED, "no search kernel for this phase-bin count and trials_per_lane");
@@ -499,7 +512,7 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
                     "8191 epochs, half that with overlapping magnitude bins)");
     const int co = o.waves_per_unit != 0
                        ? o.waves_per_unit
-                       : heuristic_co(o.precision, n_phase_bins, tq, tl.lut_lds, max_count);
+                       : gce::heuristic_co(o.precision, n_phase_bins, tq, tl.lut_lds, max_count);
     if (co == 2 && !gce::search_variant_exists(o.precision, n_phase_bins, tq, 2))
         return fail(GCE_EUNSUPPORTED,
                     "no two-wave search kernel for this phase-bin count and trials_per_lane");

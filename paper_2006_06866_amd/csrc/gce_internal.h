@@ -167,8 +167,12 @@ int validate_shape(const int64_t *off, int64_t n_curves, int64_t n_p, int64_t n_
 // Largest count of a histogram cell, a marginal or a pair of phase slots.
 int count_bound(int32_t max_n, int32_t n_phase, int32_t phase_overlap, int32_t mag_overlap,
                 int32_t *max_count);
-// Pdot trials per lane chosen by the measured heuristic.
-int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count);
+// Waves per work unit chosen by the measured heuristic (1 or 2).
+int heuristic_co(int precision, int n_phase, int tq, int lut_lds, int32_t max_count);
+// Pdot trials per lane chosen by the measured heuristic; waves_per_unit is
+// the requested count (0 automatic).
+int heuristic_tq(int precision, int n_phase, int64_t n_pd, int32_t max_count,
+                 int waves_per_unit = 0);
 // Whether a tiling has a kernel and fits the LDS and count limits.
 bool tiling_fits(int precision, int n_phase, int tq, int lut_lds, int32_t max_count);
 // Fill the shape fields of dp (pointers untouched).

@@ -67,8 +67,8 @@ extern "C" int gce_search_noalloc(const double *times, const double *mags,
     int32_t max_count = 0;
     rc = gce::count_bound(max_n, n_phase_bins, 0, 0, &max_count);
     if (rc != GCE_OK) return rc;
-    // FP64, the heuristic trials per lane, the c ln c table in global
-    // memory, curves in their given order (no schedule to upload)
+    // FP64, the heuristic trials and waves per work unit, the c ln c table
+    // in global memory, curves in their given order (no schedule to upload)
     const gce_opts o{};
     const int tq = gce::heuristic_tq(GCE_PRECISION_FP64, n_phase_bins, n_pdots, max_count);
     if (!gce::tiling_fits(GCE_PRECISION_FP64, n_phase_bins, tq, 0, max_count))
@@ -76,6 +76,7 @@ extern "C" int gce_search_noalloc(const double *times, const double *mags,
     DevPlan dp{};
     gce::fill_shape(dp, n_curves, n_periods, n_pdots, n_phase_bins, n_mag_bins, tq, max_count,
                     o, 0);
+    dp.co = gce::heuristic_co(GCE_PRECISION_FP64, n_phase_bins, tq, 0, max_count);
     if (dp.n_units > gce::kMaxUnits)
         return gce::set_error(GCE_EINVAL, "too many work units for one launch");
     const gce::WorkspaceLayout lay = gce::workspace_layout(dp, curve_offsets[n_curves]);

@@ -215,9 +215,11 @@ def test_noalloc_entry_point_bounds_its_workspace_on_host():
     _ensure_built()
     L = gce.lib()
     dummy = ctypes.c_void_p(16)   # never dereferenced: the calls fail first
-    off = np.arange(0, 513 * 600, 600, dtype=np.int64)   # 512 curves x 600 epochs
+    # 1,024 curves x 600 epochs, 20,000 x 64 trials: 2.6 M work units at
+    # 8 trials per lane, beyond the array
+    off = np.arange(0, 1025 * 600, 600, dtype=np.int64)
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    rc = L.gce_search_noalloc(dummy, dummy, offp, 512, dummy, 20000, dummy, 64, 10, 5, None,
+    rc = L.gce_search_noalloc(dummy, dummy, offp, 1024, dummy, 20000, dummy, 64, 10, 5, None,
                               dummy, None)
     assert rc == -4
     assert b"scratch" in L.gce_status_string(rc)

@@ -14,10 +14,25 @@ from paper_2006_06866_amd import synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def _info(tq, wpu=1, table=0):
+    return {"trials_per_lane": tq, "waves_per_unit": wpu, "table_in_lds": table}
+
+
+def test_search_kernel_names():
+    """The kernel a plan launches, as the profiler names it: compiled bin
+    counts or 0 (any count), trials, table in LDS (not for the first of two
+    launches), bin kind; two waves per unit are k_search_co."""
+    assert (bench.search_kernel_name(0, 10, False, _info(8, 2))
+            == "gce::k_search_co<0, 10, 8, 0, 0>")
+    assert (bench.search_kernel_name(1, 50, True, _info(2, 2, 1))
+            == "gce::k_search_co<1, 50, 2, 1, 1>")
+    assert bench.search_kernel_name(0, 64, False, _info(4, 1, 2)) == "gce::k_search<0, 0, 4, 0, 0>"
+
+
 def test_roofline_flop_form_and_slot_model():
     w = synth.make_config(2)
     kernel_s = 0.0525
-    r = bench.roofline(0, w, kernel_s, 2, 4, as_recorded=False)
+    r = bench.roofline(0, w, kernel_s, 2, _info(4), as_recorded=False)
     rate = w.point_trials / kernel_s
     assert r["flops_per_point_trial"] == 8.0 and r["lane_ops_per_point_trial"] == 7.0
     assert math.isclose(r["achieved"], 8.0 * rate / 1e12)
@@ -28,7 +43,7 @@ def test_roofline_flop_form_and_slot_model():
     # 600 epochs x 4 trials
     flush = 5 * 10 * 2 * 5.0 / (4 * 600)
     assert math.isclose(r["valu_slots_per_point_trial"], 4.5 + flush)
-    s = bench.roofline(1, w, kernel_s, 2, 8, as_recorded=False)
+    s = bench.roofline(1, w, kernel_s, 2, _info(8, 2), as_recorded=False)
     assert math.isclose(s["frac"], s["achieved"] / 157.3)
     assert math.isclose(s["valu_slots_per_point_trial"], 3.0 + 4.5 / 8 + 5 * 10 * 4 * 5.0 / (8 * 600))
     assert r["traffic"] is None and r["valu_busy_counters"] is None
@@ -47,14 +62,18 @@ def test_records_count_only_for_the_profiled_code():
             texts.append(f.read())
     assert bench.search_source_sha256([t + "\n// a note\n\n" for t in texts]) == sha
     assert bench.search_source_sha256([texts[0] + "\nint x;\n", *texts[1:]]) != sha
+    k64 = rec["kernels"]["c2_fp64"]["kernel"]
     if rec["kernel_source_sha256"] == sha:
-        c = bench.measured_counters(2, 0)
+        c = bench.measured_counters(2, 0, k64)
         assert c is not None and 0.0 < c["valu_busy"] <= 1.05
-        assert c["kernel"] == rec["kernels"]["c2_fp64"]["kernel"]
+        assert c["kernel"] == k64
     else:
-        assert bench.measured_counters(2, 0) is None
+        assert bench.measured_counters(2, 0, k64) is None
+    # another kernel (tiling) than the recorded one: no record
+    assert bench.measured_counters(2, 0, "gce::k_search<0, 10, 2, 0, 0>") is None
     if tra["kernel_source_sha256"] == sha:
-        assert bench.measured_traffic(2, 0) == tra["per_launch_bytes"]["k_search<fp64>"]
+        assert bench.measured_traffic(2, k64) == tra["per_launch_bytes"][k64]
     else:
-        assert bench.measured_traffic(2, 0) is None
-    assert bench.measured_traffic(2, 0, as_recorded=False) is None
+        assert bench.measured_traffic(2, k64) is None
+    assert bench.measured_traffic(2, "gce::k_search<0, 10, 2, 0, 0>") is None
+    assert bench.measured_traffic(2, k64, as_recorded=False) is None

@@ -80,7 +80,11 @@ def test_noalloc_allocates_nothing_and_bounds_its_shapes():
     assert_cube_close(cube.cpu().numpy(), oc, w, "injected")
     bf = gce.best_fields(best)
     assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "injected")
-    big = synth.make_config(2)   # 2.6 M work units: beyond the array
+    c2 = synth.make_config(2)   # twice over: 2.6 M work units, beyond the array
+    big = synth.Workload("c2 twice", np.concatenate([c2.times, c2.times]),
+                         np.concatenate([c2.mags, c2.mags]),
+                         np.concatenate([c2.offsets, c2.offsets[1:] + c2.offsets[-1]]),
+                         c2.periods, c2.pdots, c2.n_phase, c2.n_mag)
     db = upload(big)
     with pytest.raises(gce.GceError) as ei:
         gce.search(db[0], db[1], big.offsets, db[2], db[3], big.n_phase, big.n_mag,
