@@ -70,8 +70,8 @@ def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
     that floors phase * n_phase, the histogram address (4 slots); split two
     FP32 fmas (Pdot term, rounding) at half a slot, fract and the address
     (3 slots).  Per epoch and lane, shared by the lane's tq Pdot trials:
-    FP64 x and x^2 (2); split x and frac(x) in FP64, two conversions to
-    float and x^2 in FP32 (4.5).
+    FP64 x and x^2 (2); split x and frac(x) in FP64, the conversion of
+    frac(x) to float and x^2 = dt^2 (1/P)^2 in FP32 (3.5).
 
     Segment flush, per magnitude segment, phase bin and packed word (two
     trials): the marginal add, two table-offset extractions and two FP64
@@ -83,7 +83,7 @@ def valu_instr_per_point_trial(precision, tq, w, entries_per_point=1.0):
     With overlapping magnitude bins an epoch is folded once per magnitude
     bin that holds it: the per-point part scales by the entries per epoch."""
     import numpy as np
-    point = (4.0 + 2.0 / tq if precision == 0 else 3.0 + 4.5 / tq) * entries_per_point
+    point = (4.0 + 2.0 / tq if precision == 0 else 3.0 + 3.5 / tq) * entries_per_point
     k = 5.0 + (1.0 if w.phase_overlap else 0.0)
     words = (tq + 1) // 2
     lengths = np.asarray(w.lengths, dtype=np.float64)

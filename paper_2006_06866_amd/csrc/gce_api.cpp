@@ -373,11 +373,14 @@ gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_poin
     L.off = take(sizeof(int64_t) * (size_t)(dp.n_curves + 1));
     L.order = take(sizeof(int32_t) * (size_t)dp.n_curves);
     L.lut = take(sizeof(double) * (size_t)(dp.max_count + 1));
-    L.dt = take(sizeof(double) * (size_t)total_points * (dp.mag_overlap ? 2 : 1));
+    const size_t entries = (size_t)total_points * (dp.mag_overlap ? 2 : 1);
+    L.dt = take(sizeof(double) * entries);
+    L.dt2f = take(dp.precision == GCE_PRECISION_SPLIT_FP32 ? sizeof(float) * entries : 0);
     L.seg = take(sizeof(int32_t) * (size_t)dp.n_curves * (size_t)(dp.n_mag + 1));
     L.curve_ok = take(sizeof(int32_t) * (size_t)dp.n_curves);
     L.grid_ok = take(sizeof(int32_t));
     L.inv_p = take(sizeof(double) * (size_t)dp.n_p);
+    L.inv_p2f = take(dp.precision == GCE_PRECISION_SPLIT_FP32 ? sizeof(float) * (size_t)dp.n_p : 0);
     L.half_pd = take(sizeof(double) * (size_t)dp.n_pd);
     L.half_pd32 = take(sizeof(float) * (size_t)dp.n_pd);
     L.partials = take(sizeof(Partial) * (size_t)dp.n_units);
@@ -392,10 +395,14 @@ void gce::bind_workspace(DevPlan &dp, char *w, const WorkspaceLayout &L)
     dp.order = reinterpret_cast<const int32_t *>(w + L.order);
     dp.lut = reinterpret_cast<const double *>(w + L.lut);
     dp.dt_sorted = reinterpret_cast<double *>(w + L.dt);
+    dp.dt2f_sorted =
+        dp.precision == GCE_PRECISION_SPLIT_FP32 ? reinterpret_cast<float *>(w + L.dt2f) : nullptr;
     dp.seg = reinterpret_cast<int32_t *>(w + L.seg);
     dp.curve_ok = reinterpret_cast<int32_t *>(w + L.curve_ok);
     dp.grid_ok = reinterpret_cast<int32_t *>(w + L.grid_ok);
     dp.inv_p = reinterpret_cast<double *>(w + L.inv_p);
+    dp.inv_p2f =
+        dp.precision == GCE_PRECISION_SPLIT_FP32 ? reinterpret_cast<float *>(w + L.inv_p2f) : nullptr;
     dp.half_pd = reinterpret_cast<double *>(w + L.half_pd);
     dp.half_pd32 = reinterpret_cast<float *>(w + L.half_pd32);
     dp.partials = reinterpret_cast<Partial *>(w + L.partials);

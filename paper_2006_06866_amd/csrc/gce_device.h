@@ -53,9 +53,11 @@ namespace gce {
 // scalar loads into SGPRs that the vector instructions take as operands.
 #if GCE_SCALAR_EPOCHS
 typedef __attribute__((address_space(4))) const double uniform_f64;
+typedef __attribute__((address_space(4))) const float uniform_f32;
 typedef __attribute__((address_space(4))) const int32_t uniform_i32;
 #else
 typedef const double uniform_f64;
+typedef const float uniform_f32;
 typedef const int32_t uniform_i32;
 #endif
 
@@ -283,16 +285,19 @@ __device__ __forceinline__ void wave_argmin(double &h, int64_t &f)
 // split-precision binning
 // ---------------------------------------------------------------------------
 // Split-precision bin.  FP64 forms x = dt / P and frac(x) (the step whose
-// magnitude needs it); FP32 converts frac(x) and x^2 to float, applies each
-// trial's Pdot term with one fma, reduces mod 1 (v_fract_f32, exact) and
-// floors n * phase by adding 1.5 * 2^23 in one fma: with the FP32 rounding
-// mode set toward minus infinity (split_round_down), the sum rounds to
-// 1.5 * 2^23 + floor(n * phase) of the exact product, and the float's low
-// mantissa bits hold that integer.  The phase is below 1, so the slot is in
-// [0, n).  Every FP32 instruction between split_round_down and
-// split_round_nearest rounds down: the conversions of frac(x) and x to float
-// and the Pdot fma err by under one ulp each (frac(x): 2^-24 cycle; the Pdot
-// term: about 3 * 2^-24 of its size), always in the same direction.
+// magnitude needs it); FP32 converts frac(x) to float, forms x^2 as the
+// product of dt^2 and (1/P)^2 (each rounded to float once, to nearest: dt^2
+// by the prepass, (1/P)^2 by the grid set-up), applies each trial's Pdot
+// term with one fma, reduces mod 1 (v_fract_f32, exact) and floors
+// n * phase by adding 1.5 * 2^23 in one fma: with the FP32 rounding mode set
+// toward minus infinity (split_round_down), the sum rounds to 1.5 * 2^23 +
+// floor(n * phase) of the exact product, and the float's low mantissa bits
+// hold that integer.  The phase is below 1, so the slot is in [0, n).  Every
+// FP32 instruction between split_round_down and split_round_nearest rounds
+// down: the conversion of frac(x), the product x^2 and the Pdot fma err by
+// under one ulp each (frac(x): 2^-24 cycle; the Pdot term: under 2.5 * 2^-23
+// of its size with the roundings of its factors), always in the same
+// direction.
 constexpr float kRoundMagic = 12582912.0f;           // 1.5 * 2^23
 constexpr uint32_t kRoundMagicBits = 0x4B400000u;    // its bit pattern
 
@@ -318,15 +323,17 @@ struct SplitPoint {
     float x2f;   // x^2
 };
 
-__device__ __forceinline__ SplitPoint split_point(double dt, double invp)
+// dt2f: dt^2 rounded to float (by the prepass); invp2f: (1/P)^2 rounded to
+// float (by the grid set-up)
+__device__ __forceinline__ SplitPoint split_point(double dt, double invp, float dt2f,
+                                                  float invp2f)
 {
     const double x = dt * invp;
     SplitPoint sp;
     // FP64 only where the magnitude of x demands it (x and its fraction),
-    // the square in FP32 (a half-slot instruction)
+    // the square as dt^2 (1/P)^2 in FP32 (a half-slot instruction)
     sp.xf = (float)__builtin_amdgcn_fract(x);
-    const float xs = (float)x;
-    sp.x2f = xs * xs;
+    sp.x2f = dt2f * invp2f;
     return sp;
 }
 

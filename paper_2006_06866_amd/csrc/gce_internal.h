@@ -19,9 +19,10 @@ constexpr double kMaxSpanDays = 1e12;
 constexpr double kMinPeriod = 1e-12;
 constexpr double kMaxPeriod = 1e12;
 constexpr double kMaxAbsPdot = 1.0;
-// The split path squares x = (t - t0) / P in FP32: its plans keep x below
-// 1e16 cycles (x^2 < 1e32, far inside the float range) by accepting
-// periods of at least 1e-6 days and curves spanning at most 1e10 days.
+// The split path forms x^2 = (t - t0)^2 (1/P)^2 in FP32: its plans keep x
+// below 1e16 cycles (x^2 < 1e32, (t - t0)^2 <= 1e20 and (1/P)^2 <= 1e12, far
+// inside the float range) by accepting periods of at least 1e-6 days and
+// curves spanning at most 1e10 days.
 constexpr double kSplitMinPeriod = 1e-6;
 constexpr double kSplitMaxSpanDays = 1e10;
 // Largest count with the c ln c table in LDS: counts are kept in units of 8
@@ -83,10 +84,14 @@ struct DevPlan {
     // per-execution scratch
     double *dt_sorted;        // [total] t - t0, grouped by magnitude bin; curve
                               // c at off[c] (2 off[c] with mag_overlap)
+    float *dt2f_sorted;       // [total] (t - t0)^2 rounded to float, same order
+                              // (split path only; null for FP64 plans)
     int32_t *seg;             // [n_curves][n_mag + 1] segment starts
     int32_t *curve_ok;        // [n_curves]
     int32_t *grid_ok;         // [1]
     double *inv_p;            // [n_p] 1 / P
+    float *inv_p2f;           // [n_p] (1 / P)^2 rounded to float (split path
+                              // only; null for FP64 plans)
     double *half_pd;          // [n_pd] Pdot / 2
     float *half_pd32;         // [n_pd] Pdot / 2 rounded to float (split path)
     Partial *partials;        // [n_units]
@@ -152,8 +157,8 @@ hipError_t launch_iota_order(const DevPlan &dp, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Byte offsets of the parts of a plan's device workspace (one block).
 struct WorkspaceLayout {
-    size_t off, order, lut, dt, seg, curve_ok, grid_ok, inv_p, half_pd, half_pd32,
-        partials, stats, total;
+    size_t off, order, lut, dt, dt2f, seg, curve_ok, grid_ok, inv_p, inv_p2f, half_pd,
+        half_pd32, partials, stats, total;
 };
 
 // Record `msg` as the calling thread's last error text; returns `code`.

@@ -34,7 +34,9 @@ hipError_t launch_lut(const DevPlan &dp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// trial setup: 1/P (correctly rounded division), Pdot/2 (exact), validity.
+// trial setup: 1/P (correctly rounded division), Pdot/2 (exact), validity;
+// for the split path also (1/P)^2 and Pdot/2 rounded to float here, in the
+// default rounding, so that every kernel reading them sees the same values.
 // Grid-stride over the period and Pdot axes.  The prepass (launched first)
 // sets grid_ok to 1; any thread that meets an invalid value stores 0 (all
 // writers store the same value, so no atomics are needed).
@@ -53,7 +55,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_setup(DevPlan dp,
         const double P = periods[p];
         const bool ok = P >= p_min && P <= kMaxPeriod;       // false for NaN
         bad |= !ok;
-        dp.inv_p[p] = ok ? 1.0 / P : 1.0;
+        const double ip = ok ? 1.0 / P : 1.0;
+        dp.inv_p[p] = ip;
+        if (dp.inv_p2f) dp.inv_p2f[p] = (float)(ip * ip);
     }
     for (int64_t q = i0; q < dp.n_pd; q += stride) {
         const double Pd = pdots[q];
@@ -201,9 +205,12 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
     }
     __syncthreads();
 
-    // stable scatter of dt = t - t0 into magnitude-bin order, in chunks; an
-    // epoch in two bins is written into both segments
-    double *dst = dp.dt_sorted + (movl ? 2 * base : base);
+    // stable scatter of dt = t - t0 (and, for the split path, of dt^2
+    // rounded to float) into magnitude-bin order, in chunks; an epoch in two
+    // bins is written into both segments
+    const int64_t dbase = movl ? 2 * base : base;
+    double *dst = dp.dt_sorted + dbase;
+    float *dst2 = dp.dt2f_sorted ? dp.dt2f_sorted + dbase : nullptr;
     for (int32_t k0 = 0; k0 < n; k0 += kPrepChunk) {
         const int32_t k1 = min(n, k0 + kPrepChunk);
         for (int32_t k = k0 + threadIdx.x; k < k1; k += kPrepBlock) {
@@ -217,7 +224,9 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepass(
             int32_t pos = cur[j];
             for (int32_t k = k0; k < k1; ++k) {
                 if (jb[k - k0] == j || jb2[k - k0] == j) {
-                    dst[pos] = ok ? t[k] - t0 : 0.0;
+                    const double dt = ok ? t[k] - t0 : 0.0;
+                    dst[pos] = dt;
+                    if (dst2) dst2[pos] = (float)(dt * dt);
                     ++pos;
                 }
             }
@@ -445,8 +454,10 @@ __global__ __launch_bounds__(64) void k_debug_counts(
                 fp64_phase_bins<1, 1>(xs, x2s, hpd, (double)nph, bb);
                 b = (int)bb[0];
             } else {
+                const float ip2 = dp.inv_p2f[p];
+                const float d2f = dp.dt2f_sorted[base + k];
                 split_round_down();
-                const SplitPoint sp = split_point(dt, invp);
+                const SplitPoint sp = split_point(dt, invp, d2f, ip2);
                 const uint32_t bits = split_slot_bits(sp, ha32, (float)nph);
                 // the bin leaves through an asm operand before the mode is
                 // reset, so that its instructions all round down

@@ -140,6 +140,9 @@ void k_search(DevPlan dp, void *out_ce_v)
     // split path: (bits << 8) of slot s is 0x40000000 + 256 s (mod 2^32)
     const uint32_t split_base = (uint32_t)lane * 4u - (kRoundMagicBits << 8);
     uniform_f64 *dts = (uniform_f64 *)(dp.dt_sorted + base);
+    // split path: dt^2 and (1/P)^2 in float, their product is x^2
+    uniform_f32 *d2s = (uniform_f32 *)(PREC == kPrecSplit ? dp.dt2f_sorted + base : nullptr);
+    const float invp2f = PREC == kPrecSplit ? dp.inv_p2f[p_ok ? p : dp.n_p - 1] : 0.0f;
     uniform_i32 *segc = (uniform_i32 *)(dp.seg + (int64_t)c * (dp.n_mag + 1));
     const double *__restrict__ lut = LL ? lut_lds : dp.lut;
     uint32_t *hcol = hist + lane;
@@ -152,7 +155,7 @@ void k_search(DevPlan dp, void *out_ce_v)
     const uint32_t inc_lo = kUnit, inc_hi = kUnit << 16;
     // G epochs at a time: on the FP64 path their G * TQ round-down fmas
     // share one rounding-mode switch
-    auto fold_points = [&](const double *dt, auto g_tag) {
+    auto fold_points = [&](const double *dt, const float *d2, auto g_tag) {
         constexpr int G = decltype(g_tag)::value;
         if constexpr (PREC == kPrecFp64) {
             double x[G], x2[G];
@@ -172,7 +175,7 @@ void k_search(DevPlan dp, void *out_ce_v)
         } else {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const SplitPoint sp = split_point(dt[g], invp);
+                const SplitPoint sp = split_point(dt[g], invp, d2[g], invp2f);
 #pragma unroll
                 for (int t = 0; t < TQ; ++t) {
                     const uint32_t bits = split_slot_bits(sp, ha32[t], nphf);
@@ -352,27 +355,40 @@ void k_search(DevPlan dp, void *out_ce_v)
         int32_t k = k0;
         if (k + U <= k1) {
             double cur[U], nxt[U];
+            float cur2[U], nxt2[U];
 #pragma unroll
-            for (int uu = 0; uu < U; ++uu) cur[uu] = dts[k + uu];
+            for (int uu = 0; uu < U; ++uu) {
+                cur[uu] = dts[k + uu];
+                if constexpr (PREC == kPrecSplit) cur2[uu] = d2s[k + uu];
+            }
             while (true) {
                 const int32_t kn = k + U;
                 const bool more = kn + U <= k1;
                 if (GCE_PREFETCH && more) {
 #pragma unroll
-                    for (int uu = 0; uu < U; ++uu) nxt[uu] = dts[kn + uu];
+                    for (int uu = 0; uu < U; ++uu) {
+                        nxt[uu] = dts[kn + uu];
+                        if constexpr (PREC == kPrecSplit) nxt2[uu] = d2s[kn + uu];
+                    }
                 }
 #pragma unroll
-                for (int uu = 0; uu < U; uu += GF) fold_points(&cur[uu], std::integral_constant<int, GF>{});
+                for (int uu = 0; uu < U; uu += GF)
+                    fold_points(&cur[uu], &cur2[uu], std::integral_constant<int, GF>{});
                 k = kn;
                 if (!more) break;
 #pragma unroll
-                for (int uu = 0; uu < U; ++uu)
+                for (int uu = 0; uu < U; ++uu) {
                     cur[uu] = GCE_PREFETCH ? nxt[uu] : dts[k + uu];
+                    if constexpr (PREC == kPrecSplit)
+                        cur2[uu] = GCE_PREFETCH ? nxt2[uu] : d2s[k + uu];
+                }
             }
         }
         for (; k < k1; ++k) {
             const double d1[1] = {dts[k]};
-            fold_points(d1, std::integral_constant<int, 1>{});
+            float e1[1] = {0.0f};
+            if constexpr (PREC == kPrecSplit) e1[0] = d2s[k];
+            fold_points(d1, e1, std::integral_constant<int, 1>{});
         }
 
         flush_segment();

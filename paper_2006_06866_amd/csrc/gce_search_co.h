@@ -104,6 +104,9 @@ void k_search_co(DevPlan dp, void *out_ce_v)
     const float nphf = (float)NPH;
     const uint32_t split_base = (uint32_t)lane * 4u - (kRoundMagicBits << 8);
     uniform_f64 *dts = (uniform_f64 *)(dp.dt_sorted + base);
+    // split path: dt^2 and (1/P)^2 in float, their product is x^2
+    uniform_f32 *d2s = (uniform_f32 *)(PREC == kPrecSplit ? dp.dt2f_sorted + base : nullptr);
+    const float invp2f = PREC == kPrecSplit ? dp.inv_p2f[p_ok ? p : dp.n_p - 1] : 0.0f;
     uniform_i32 *segc = (uniform_i32 *)(dp.seg + (int64_t)c * (dp.n_mag + 1));
     const double *__restrict__ lut = LL ? lut_lds : dp.lut;
     char *lbytes = reinterpret_cast<char *>(hist);
@@ -112,7 +115,7 @@ void k_search_co(DevPlan dp, void *out_ce_v)
 
     // the fold and binning of G epochs for the lane's TQ trials (as in
     // k_search): FP64 round-down bins, or the split path's float bins
-    auto fold_points = [&](const double *dt, auto g_tag) {
+    auto fold_points = [&](const double *dt, const float *d2, auto g_tag) {
         constexpr int GE = decltype(g_tag)::value;
         if constexpr (PREC == kPrecFp64) {
             double x[GE], x2[GE];
@@ -132,7 +135,7 @@ void k_search_co(DevPlan dp, void *out_ce_v)
         } else {
 #pragma unroll
             for (int e = 0; e < GE; ++e) {
-                const SplitPoint sp = split_point(dt[e], invp);
+                const SplitPoint sp = split_point(dt[e], invp, d2[e], invp2f);
 #pragma unroll
                 for (int t = 0; t < TQ; ++t) {
                     const uint32_t bits = split_slot_bits(sp, ha32[t], nphf);
@@ -260,23 +263,32 @@ void k_search_co(DevPlan dp, void *out_ce_v)
         int32_t k = ka;
         if (k + U <= kb) {
             double cur[U];
+            float cur2[U];
 #pragma unroll
-            for (int uu = 0; uu < U; ++uu) cur[uu] = dts[k + uu];
+            for (int uu = 0; uu < U; ++uu) {
+                cur[uu] = dts[k + uu];
+                if constexpr (PREC == kPrecSplit) cur2[uu] = d2s[k + uu];
+            }
             while (true) {
                 const int32_t kn = k + U;
                 const bool more = kn + U <= kb;
 #pragma unroll
                 for (int uu = 0; uu < U; uu += GF)
-                    fold_points(&cur[uu], std::integral_constant<int, GF>{});
+                    fold_points(&cur[uu], &cur2[uu], std::integral_constant<int, GF>{});
                 k = kn;
                 if (!more) break;
 #pragma unroll
-                for (int uu = 0; uu < U; ++uu) cur[uu] = dts[k + uu];
+                for (int uu = 0; uu < U; ++uu) {
+                    cur[uu] = dts[k + uu];
+                    if constexpr (PREC == kPrecSplit) cur2[uu] = d2s[k + uu];
+                }
             }
         }
         for (; k < kb; ++k) {
             const double d1[1] = {dts[k]};
-            fold_points(d1, std::integral_constant<int, 1>{});
+            float e1[1] = {0.0f};
+            if constexpr (PREC == kPrecSplit) e1[0] = d2s[k];
+            fold_points(d1, e1, std::integral_constant<int, 1>{});
         }
         __syncthreads();   // the segment's adds of both waves are in
         flush_bins(seg_word, next_word, s1);

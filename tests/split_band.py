@@ -1,7 +1,8 @@
 """The error band of the split-precision bins.
 
 The split path forms x = (t - t0) / P and frac(x) in binary64 exactly as
-the FP64 path does, then converts frac(x) and x to binary32, squares x,
+the FP64 path does, then converts frac(x) to binary32, forms x^2 as the
+binary32 product of dt^2 and (1/P)^2 (each rounded to float from binary64),
 applies the Pdot term with one fma, reduces mod 1 and floors n * phase, every
 binary32 step rounding toward minus infinity (the bin floor is of the exact
 product).  Against the binary64 phase phi of Eq. (3), its phase differs by at
@@ -9,7 +10,7 @@ most, in cycles (|a| = |Pdot| / 2, A = |a| x^2 the Pdot term):
     frac(x) to float                 < 2^-24
     fract of a negative y            < 2^-24
     the rounding of y                < ulp(1 + A) <= 2^-23 (1 + A)
-    the Pdot term (x and x^2 to float, a to float)   < 4.5 * 2^-23 * A
+    the Pdot term (a, dt^2 and (1/P)^2 to float, their product)  < 4 * 2^-23 * A
     the binary64 rounding of phi itself              < 2^-52 (x + A)
 i.e. below E = 2^-22 + 2^-20 A + 2^-52 x (0 at x = 0, where every step is
 exact).  A split bin can therefore differ

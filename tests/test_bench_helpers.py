@@ -45,7 +45,7 @@ def test_roofline_flop_form_and_slot_model():
     assert math.isclose(r["valu_slots_per_point_trial"], 4.5 + flush)
     s = bench.roofline(1, w, kernel_s, 2, _info(8, 2), as_recorded=False)
     assert math.isclose(s["frac"], s["achieved"] / 157.3)
-    assert math.isclose(s["valu_slots_per_point_trial"], 3.0 + 4.5 / 8 + 5 * 10 * 4 * 5.0 / (8 * 600))
+    assert math.isclose(s["valu_slots_per_point_trial"], 3.0 + 3.5 / 8 + 5 * 10 * 4 * 5.0 / (8 * 600))
     assert r["traffic"] is None and r["valu_busy_counters"] is None
 
 

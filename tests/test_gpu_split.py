@@ -191,7 +191,7 @@ def test_split_random_shapes_self_consistent():
 
 
 def test_split_range_limits_mark_curves_invalid():
-    """The split path squares x = (t - t0) / P in FP32, so its plans take
+    """The split path forms x^2 = (t - t0)^2 / P^2 in FP32, so its plans take
     periods of at least 1e-6 d and spans of at most 1e10 d: a shorter period
     invalidates the grid (every curve), a longer span its curve, where the
     FP64 path accepts both.  Debug counts of valid split trials still total

@@ -113,14 +113,17 @@ def _rd32(v):
 
 def _split_phase(dt, period, pdot):
     """The split path's phase, step by step as the kernel computes it: x and
-    frac(x) in binary64 (to nearest), then every binary32 operation rounded
-    toward minus infinity; Pdot/2 rounded to nearest float."""
+    frac(x) in binary64 (to nearest); dt^2 and (1/P)^2 formed in binary64
+    and rounded to nearest float (the prepass, the work unit's set-up), and
+    Pdot/2 rounded to nearest float; then every binary32 operation rounded
+    toward minus infinity."""
     invp = 1.0 / period
     x = dt * invp
     f = x - math.floor(x)
     xf = _rd32(Fraction(f))
-    xs = _rd32(Fraction(x))
-    x2f = _rd32(Fraction(float(xs)) * Fraction(float(xs)))
+    d2f = np.float32(dt * dt)
+    ip2f = np.float32(invp * invp)
+    x2f = _rd32(Fraction(float(d2f)) * Fraction(float(ip2f)))
     ha = np.float32(0.5 * pdot)
     y = _rd32(Fraction(float(xf)) - Fraction(float(ha)) * Fraction(float(x2f)))
     return _rd32(Fraction(float(y)) - math.floor(float(y)))
