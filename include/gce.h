@@ -44,10 +44,10 @@
  *    [1e-12, 1e12] days or NaN, |Pdot| > 1 or NaN, epochs of one curve
  *    spanning more than 1e12 days) cannot be reported synchronously: the affected
  *    curves (all curves for a bad grid) get flat_index = -1, ce_min = NaN and
- *    NaN CE values.  Split-precision plans (GCE_PRECISION_SPLIT_FP32) square
- *    x = (t - t0) / P in FP32 and accept only periods of at least 1e-6 days
- *    and curves spanning at most 1e10 days (x below 1e16 cycles); other
- *    values are bad data values in the same sense.
+ *    NaN CE values.  Split-precision plans (GCE_PRECISION_SPLIT_FP32) form
+ *    x^2 = (t - t0)^2 / P^2 in FP32 and accept only periods of at least
+ *    1e-6 days and curves spanning at most 1e10 days (x below 1e16 cycles);
+ *    other values are bad data values in the same sense.
  *  - Test hook: with the environment variable GCE_FAIL_ALLOC=1, the entry
  *    points that allocate device memory (gce_plan_create, gce_search,
  *    gce_autotune) return GCE_ENOMEM after checking their arguments, before
