@@ -172,15 +172,17 @@ def cpu_baseline(w, gpu_cube_rows, budget_s):
 
 
 def timed_leg(gce, torch, np, w, dev, inputs, precision, tq, steps, warmup, cube_on,
-              graph=False, table=0):
+              graph=False, table=0, refine=0):
     """Warm up, then time exactly `steps` whole searches.  With graph=True the
-    search (all four kernels) is captured once in a HIP graph and the timed
+    search (all its kernels) is captured once in a HIP graph and the timed
     steps are graph replays; the search kernel's own duration then comes
-    from a separate eager pass with events."""
+    from a separate eager pass with events.  refine: the split path's FP64
+    confirmation of each curve's `refine` best work units (part of the timed
+    search)."""
     plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
                     precision=precision, trials_per_lane=tq,
                     phase_overlap=w.phase_overlap, table_placement=table,
-                    mag_overlap=w.mag_overlap, device=dev)
+                    mag_overlap=w.mag_overlap, refine_units=refine, device=dev)
     return _time_plan(torch, np, plan, inputs, steps, warmup, cube_on, graph)
 
 
@@ -395,6 +397,10 @@ def split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64, cube32, bes
     strict = bf32["flat_index"] == bf64["flat_index"]
     out = {"reference": "fp64 path (bins bit-exact to the oracle's)",
            "best_equal_strict": f"{int(strict.sum())}/{w.n_curves}"}
+    ok = (bf64["flat_index"] >= 0) & (bf32["flat_index"] >= 0)
+    if ok.any():
+        out["max_abs_dH_reported_minimum"] = float(
+            np.max(np.abs(bf32["ce_min"][ok] - bf64["ce_min"][ok])))
     if "inj_p" in w.truth:
         found = (np.asarray(w.truth["inj_p"]) >= 0) & (
             bf64["period_index"] == w.truth["inj_p"]) & (bf64["pdot_index"] == w.truth["inj_q"])
@@ -488,7 +494,7 @@ def cpu_baseline_samples(np, w, ci, fi, g64, g32, bf64):
 
 
 def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, tq,
-                 table, do_split, as_recorded):
+                 table, do_split, as_recorded, refine=0):
     """Both legs of one workload.  Returns (summary dict, FP64 leg state)."""
     inputs = tuple(torch.from_numpy(a).to(dev) for a in (w.times, w.mags, w.periods, w.pdots))
     pt = w.point_trials
@@ -511,15 +517,21 @@ def run_workload(gce, torch, np, w, dev, config, steps, warmup, graph, cube_on, 
              "cube32": None, "el64": el64}
     if do_split:
         plan32, cube32, best32, el32, k32 = timed_leg(
-            gce, torch, np, w, dev, inputs, 1, tq, steps, warmup, cube_on, graph, table)
+            gce, torch, np, w, dev, inputs, 1, tq, steps, warmup, cube_on, graph, table,
+            refine)
         log(f"c{config} split: {el32 / steps * 1e3:.2f} ms/step, kernel {k32 * 1e3:.2f} ms")
         split = {"value": pt * steps / el32, "unit": "point-trials/s",
                  "ms_per_step": el32 / steps * 1e3, "speedup_vs_fp64": el64 / el32,
                  "trials_per_lane": plan32.info()["trials_per_lane"],
                  "table_in_lds": int(plan32.info()["table_in_lds"]),
                  "waves_per_unit": plan32.info()["waves_per_unit"],
+                 "refine_units": plan32.info()["refine_units"],
                  "roofline": roofline(1, w, k32, config, plan32.info(), entries,
                                       as_recorded)}
+        if split["refine_units"]:
+            split["reported_minimum"] = (
+                f"FP64 minimum over each curve's {split['refine_units']} work units with "
+                "the smallest split minima (split cube, split moments)")
         split.update(split_vs_fp64(torch, np, gce, w, inputs, plan64, plan32, cube64,
                                    cube32, best64, best32))
         res["split"] = split
@@ -537,6 +549,9 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="minimum only (no CE cube)")
     ap.add_argument("--trials-per-lane", type=int, default=0)
     ap.add_argument("--no-split", action="store_true", help="skip the split leg")
+    ap.add_argument("--split-refine", type=int, default=4, metavar="K",
+                    help="split leg: confirm each curve's minimum in FP64 over its K best "
+                         "work units (0: the split minimum as found)")
     ap.add_argument("--table", choices=["auto", "global", "lds"], default="auto",
                     help="where the search kernel reads its c ln c table")
     ap.add_argument("--mag-overlap", action="store_true",
@@ -607,7 +622,7 @@ def main():
                    and args.table == "auto" and args.trials_per_lane == 0)
     head, st = run_workload(gce, torch, np, w, dev, args.config, args.steps, args.warmup,
                             graph, cube_on, args.trials_per_lane, TABLES[args.table],
-                            not args.no_split, as_recorded)
+                            not args.no_split, as_recorded, args.split_refine)
     plan64, cube64, best64, inputs = st["plan64"], st["cube64"], st["best64"], st["inputs"]
     el64 = st["el64"]
     bf64 = gce.best_fields(best64)
@@ -721,7 +736,7 @@ def main():
         cube_e = cfg != 6
         res, st = run_workload(gce, torch, np, we, dev, cfg,
                                args.extra_steps if cube_e else 1, 1, graph, cube_e, 0, 0,
-                               not args.no_split, True)
+                               not args.no_split, True, args.split_refine)
         res["workload"] = WORKLOADS[cfg]
         res["timing"] = "hip-graph replay" if graph else "eager launches"
         bfe = gce.best_fields(st["best64"])

@@ -205,6 +205,19 @@ typedef struct {
                                 bins at 1, 2 and 4 (GCE_EUNSUPPORTED
                                 elsewhere); automatic takes 2 there when one
                                 wave's histograms would hold 8 KiB or more. */
+    int32_t refine_units;    /* split path only (no effect on FP64 plans):
+                                0 = none; k in [1, 64] = after the split
+                                search, the k work units of each curve with
+                                the smallest split minima are searched again
+                                with the FP64 kernel, and the curve's reported
+                                minimum (flat, period and Pdot index, ce_min)
+                                is the FP64 minimum over those units' trials,
+                                its CE value the FP64 one; ce_mean and ce_std
+                                stay those of the split CE values over the
+                                whole grid, and the significance is formed
+                                from them and the FP64 ce_min.  The CE cube
+                                keeps the split values.  About k work units
+                                per curve of extra FP64 work. */
 } gce_opts;
 
 #define GCE_TABLE_AUTO 0
@@ -287,6 +300,8 @@ typedef struct {
     int64_t work_units;         /* work units of one search launch */
     int64_t workspace_bytes;    /* device workspace held by the plan */
     int32_t waves_per_unit;     /* waves that search one work unit: 1 or 2 */
+    int32_t refine_units;       /* work units per curve searched again in
+                                   FP64 (split plans with refine_units) */
 } gce_plan_info_t;
 
 /* Fill *info for the plan.  Returns GCE_EINVAL for NULL arguments. */
@@ -351,9 +366,10 @@ int gce_plan_destroy(gce_plan_t plan);
  * error of the calling thread's last failing call. */
 const char *gce_status_string(int status);
 
-/* Library version string ("gce-mi355x 0.3.0 (gfx950)"; 0.2.0 appended
+/* Library version string ("gce-mi355x 0.4.0 (gfx950)"; 0.2.0 appended
  * mag_overlap to gce_opts and to gce_autotune's arguments, 0.3.0 appended
- * waves_per_unit to gce_opts and to gce_plan_info_t). */
+ * waves_per_unit to gce_opts and to gce_plan_info_t, 0.4.0 appended
+ * refine_units to both). */
 const char *gce_version(void);
 
 #ifdef __cplusplus

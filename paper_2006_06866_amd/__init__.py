@@ -53,13 +53,14 @@ class _Info(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
                 ("lds_bytes_per_wave", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
                 ("work_units", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("waves_per_unit", ctypes.c_int32)]
+                ("waves_per_unit", ctypes.c_int32), ("refine_units", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("trials_per_lane", ctypes.c_int32),
                 ("phase_overlap", ctypes.c_int32), ("table_placement", ctypes.c_int32),
-                ("mag_overlap", ctypes.c_int32), ("waves_per_unit", ctypes.c_int32)]
+                ("mag_overlap", ctypes.c_int32), ("waves_per_unit", ctypes.c_int32),
+                ("refine_units", ctypes.c_int32)]
 
 
 _lib = None
@@ -159,15 +160,18 @@ class Plan:
     or 1, 2, 4, 8; phase_overlap / mag_overlap: 50%-overlapping phase /
     magnitude bins (Sec. 2.3); table_placement: TABLE_AUTO, TABLE_GLOBAL or
     TABLE_LDS for the c ln c table; waves_per_unit: 0 (automatic), 1, or 2
-    waves sharing one copy of a work unit's histograms.  Options map one to
-    one onto gce_opts.
+    waves sharing one copy of a work unit's histograms; refine_units (split
+    path): 0, or the number of each curve's best split work units searched
+    again in FP64 for the reported minimum.  Options map one to one onto
+    gce_opts.
     """
 
     def __init__(self, offsets, n_periods: int, n_pdots: int, n_phase: int,
                  n_mag: int, precision: int = PRECISION_FP64,
                  trials_per_lane: int = 0, phase_overlap: bool = False,
                  table_placement: int = TABLE_AUTO, mag_overlap: bool = False,
-                 waves_per_unit: int = 0, device: Optional[torch.device] = None):
+                 waves_per_unit: int = 0, refine_units: int = 0,
+                 device: Optional[torch.device] = None):
         self._h = None
         self.offsets = _host_offsets(offsets)
         self.n_curves = int(self.offsets.size - 1)
@@ -181,7 +185,8 @@ class Plan:
         self.phase_overlap = bool(phase_overlap)
         self.mag_overlap = bool(mag_overlap)
         opts = _Opts(self.precision, int(trials_per_lane), int(self.phase_overlap),
-                     int(table_placement), int(self.mag_overlap), int(waves_per_unit))
+                     int(table_placement), int(self.mag_overlap), int(waves_per_unit),
+                     int(refine_units))
         h = ctypes.c_void_p()
         L = lib()
         _check(L.gce_plan_create(ctypes.byref(h),

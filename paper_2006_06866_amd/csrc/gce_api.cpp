@@ -266,6 +266,12 @@ struct gce_plan_s {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     uint64_t key_hash = 0;
+    // FP64 confirmation of a split search's minima (gce_opts.refine_units):
+    // work units per curve and the device lists and results
+    int32_t refine_k = 0;
+    int64_t *refine_list = nullptr;
+    gce::Partial *refine_partials = nullptr;
+    gce::UnitStats *refine_stats = nullptr;
     // search-kernel timing ring (gce_plan_set_timing)
     std::vector<hipEvent_t> ev_start, ev_stop;
     int64_t n_timed = 0;
@@ -360,7 +366,8 @@ void gce::fill_shape(DevPlan &dp, int64_t n_curves, int64_t n_p, int64_t n_pd,
     dp.co = 1;
 }
 
-gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_points)
+gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_points,
+                                           int32_t refine_units)
 {
     const size_t A = 256;
     size_t sz = 0;
@@ -385,6 +392,10 @@ gce::WorkspaceLayout gce::workspace_layout(const DevPlan &dp, int64_t total_poin
     L.half_pd32 = take(sizeof(float) * (size_t)dp.n_pd);
     L.partials = take(sizeof(Partial) * (size_t)dp.n_units);
     L.stats = take(sizeof(UnitStats) * (size_t)dp.n_units);
+    const size_t nref = (size_t)refine_units * (size_t)dp.n_curves;
+    L.refine_list = take(sizeof(int64_t) * nref);
+    L.refine_partials = take(sizeof(Partial) * nref);
+    L.refine_stats = take(sizeof(UnitStats) * nref);
     L.total = sz;
     return L;
 }
@@ -453,7 +464,7 @@ int64_t split_by_length(int precision, int n_phase, int n_mag, int tq, int phase
 
 extern "C" {
 
-const char *gce_version(void) { return "gce-mi355x 0.3.0 (gfx950)"; }
+const char *gce_version(void) { return "gce-mi355x 0.4.0 (gfx950)"; }
 
 const char *gce_status_string(int status)
 {
@@ -503,6 +514,8 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         return fail(GCE_EINVAL, "table_placement must be 0, 1 or 2");
     if (o.waves_per_unit != 0 && o.waves_per_unit != 1 && o.waves_per_unit != 2)
         return fail(GCE_EINVAL, "waves_per_unit must be 0, 1 or 2");
+    if (o.refine_units < 0 || o.refine_units > gce::kMaxRefineUnits)
+        return fail(GCE_EINVAL, "refine_units must be in [0, 64]");
     int32_t max_count = 0;
     rc = gce::count_bound(max_n, n_phase_bins, o.phase_overlap, o.mag_overlap, &max_count);
     if (rc != GCE_OK) return rc;
@@ -528,6 +541,14 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         return fail(GCE_EUNSUPPORTED,
                     "a block's LDS would exceed 64 KiB: lower trials_per_lane or keep the "
                     "table in global memory");
+    // the FP64 confirmation runs the FP64 kernel of the same tiling, with the
+    // table in global memory, over the chosen work units
+    const int32_t refine_k = o.precision == GCE_PRECISION_SPLIT_FP32 ? o.refine_units : 0;
+    if (refine_k > 0 &&
+        (!gce::search_variant_exists(GCE_PRECISION_FP64, n_phase_bins, tq, co) ||
+         gce::search_lds_bytes(GCE_PRECISION_FP64, n_phase_bins, tq, 0, max_count, co) >
+             gce::kMaxLdsBytes))
+        return fail(GCE_EUNSUPPORTED, "no FP64 search kernel of this tiling for refine_units");
 
     DevPlan shape{};
     gce::fill_shape(shape, n_curves, n_periods, n_pdots, n_phase_bins, n_mag_bins, tq,
@@ -576,7 +597,8 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
                (curve_offsets[b + 1] - curve_offsets[b]);
     });
 
-    const gce::WorkspaceLayout lay = gce::workspace_layout(dp, pl->total_points);
+    pl->refine_k = refine_k;
+    const gce::WorkspaceLayout lay = gce::workspace_layout(dp, pl->total_points, refine_k);
     pl->ws_bytes = lay.total;
     hipError_t e = hipMalloc(&pl->ws, lay.total);
     if (e != hipSuccess) {
@@ -585,6 +607,12 @@ int gce_plan_create(gce_plan_t *plan_out, const int64_t *curve_offsets,
         return fail(GCE_ENOMEM, "hipMalloc of the workspace failed");
     }
     gce::bind_workspace(dp, static_cast<char *>(pl->ws), lay);
+    if (refine_k > 0) {
+        char *w = static_cast<char *>(pl->ws);
+        pl->refine_list = reinterpret_cast<int64_t *>(w + lay.refine_list);
+        pl->refine_partials = reinterpret_cast<gce::Partial *>(w + lay.refine_partials);
+        pl->refine_stats = reinterpret_cast<gce::UnitStats *>(w + lay.refine_stats);
+    }
 
     e = hipMemcpy(const_cast<int64_t *>(dp.off), curve_offsets,
                   sizeof(int64_t) * (size_t)(n_curves + 1), hipMemcpyHostToDevice);
@@ -648,6 +676,24 @@ int gce_plan_execute(gce_plan_t pl, const double *times, const double *mags,
     }
     e = gce::launch_epilogue(dp, out_best, s);
     if (e != hipSuccess) return fail_hip(e, "epilogue launch");
+    if (pl->refine_k > 0) {
+        // the FP64 kernel of the same tiling over each curve's refine_k best
+        // split work units, then their FP64 minimum into out_best
+        e = gce::launch_refine_select(dp, pl->refine_k, pl->refine_list, s);
+        if (e != hipSuccess) return fail_hip(e, "refine selection launch");
+        DevPlan r = dp;
+        r.precision = GCE_PRECISION_FP64;
+        r.lut_lds = 0;
+        r.unit_list = pl->refine_list;
+        r.unit0 = 0;
+        r.n_units = (int64_t)pl->refine_k * dp.n_curves;
+        r.partials = pl->refine_partials;
+        r.stats = pl->refine_stats;
+        e = gce::launch_search(r, nullptr, s);
+        if (e != hipSuccess) return fail_hip(e, "refine search launch");
+        e = gce::launch_refine_merge(dp, pl->refine_k, pl->refine_partials, out_best, s);
+        if (e != hipSuccess) return fail_hip(e, "refine merge launch");
+    }
     return GCE_OK;
 }
 
@@ -738,6 +784,7 @@ int gce_plan_get_info(gce_plan_t pl, gce_plan_info_t *info)
     info->work_units = pl->dp.n_units;
     info->workspace_bytes = (int64_t)pl->ws_bytes;
     info->waves_per_unit = pl->dp.co;
+    info->refine_units = pl->refine_k;
     return GCE_OK;
 }
 

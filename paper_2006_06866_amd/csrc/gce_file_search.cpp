@@ -32,7 +32,7 @@ int usage()
     std::fprintf(stderr,
                  "usage: gce_file_search DIR N_PHASE N_MAG [--split] [--phase-overlap] "
                  "[--mag-overlap] [--cube] [--table global|lds] [--trials-per-lane T] "
-                 "[--waves-per-unit W] [--device D]\n");
+                 "[--waves-per-unit W] [--refine-units K] [--device D]\n");
     return 2;
 }
 
@@ -116,6 +116,7 @@ int main(int argc, char **argv)
             else return usage();
         } else if (a == "--trials-per-lane" && i + 1 < argc) opts.trials_per_lane = std::atoi(argv[++i]);
         else if (a == "--waves-per-unit" && i + 1 < argc) opts.waves_per_unit = std::atoi(argv[++i]);
+        else if (a == "--refine-units" && i + 1 < argc) opts.refine_units = std::atoi(argv[++i]);
         else if (a == "--device" && i + 1 < argc) device = std::atoi(argv[++i]);
         else return usage();
     }

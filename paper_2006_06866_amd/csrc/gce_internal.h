@@ -14,6 +14,7 @@ namespace gce {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxPoints = 65535;    // 16-bit histogram counters
 constexpr int kMaxMagBins = 255;
+constexpr int kMaxRefineUnits = 64;  // work units per curve of an FP64 confirmation
 constexpr int kMaxPhaseBins = 128;   // LDS budget of the generic kernel
 constexpr double kMaxSpanDays = 1e12;
 constexpr double kMinPeriod = 1e-12;
@@ -64,6 +65,10 @@ struct DevPlan {
                               // launch: the end of its unit range
     int64_t unit0;            // first work unit of a search launch (0 unless
                               // the batch is searched in two launches)
+    const int64_t *unit_list; // null, or the work units a search launch takes
+                              // (entries unit0 .. n_units - 1 of the list;
+                              // unit i's minimum and moments go to
+                              // partials[i], stats[i])
     int32_t max_count;        // largest count of a histogram cell, a marginal
                               // or a pair of phase slots: the longest curve,
                               // doubled with overlapping magnitude bins and
@@ -107,6 +112,14 @@ hipError_t launch_prepass(const DevPlan &dp, const double *times,
 hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s);
 hipError_t launch_epilogue(const DevPlan &dp, gce_best_t *out_best,
                            hipStream_t s);
+// FP64 confirmation of a split search's minima: per curve the k work units
+// with the smallest split minima (into `list`, k per curve in schedule
+// order), then, after the FP64 search over them has written `ref` (k
+// partials per curve), each curve's FP64 minimum over those units into
+// out_best (gce_opts.refine_units).
+hipError_t launch_refine_select(const DevPlan &dp, int32_t k, int64_t *list, hipStream_t s);
+hipError_t launch_refine_merge(const DevPlan &dp, int32_t k, const Partial *ref,
+                               gce_best_t *out_best, hipStream_t s);
 hipError_t launch_debug_counts(const DevPlan &dp, const int64_t *trial_curve,
                                const int64_t *trial_flat, int64_t n_trials,
                                uint32_t *out_counts, hipStream_t s);
@@ -158,7 +171,7 @@ hipError_t launch_iota_order(const DevPlan &dp, hipStream_t s);
 // Byte offsets of the parts of a plan's device workspace (one block).
 struct WorkspaceLayout {
     size_t off, order, lut, dt, dt2f, seg, curve_ok, grid_ok, inv_p, inv_p2f, half_pd,
-        half_pd32, partials, stats, total;
+        half_pd32, partials, stats, refine_list, refine_partials, refine_stats, total;
 };
 
 // Record `msg` as the calling thread's last error text; returns `code`.
@@ -183,8 +196,10 @@ bool tiling_fits(int precision, int n_phase, int tq, int lut_lds, int32_t max_co
 // Fill the shape fields of dp (pointers untouched).
 void fill_shape(DevPlan &dp, int64_t n_curves, int64_t n_p, int64_t n_pd, int32_t n_phase,
                 int32_t n_mag, int32_t tq, int32_t max_count, const gce_opts &o, int32_t lut_lds);
-// Workspace layout of a filled shape holding total_points epochs.
-WorkspaceLayout workspace_layout(const DevPlan &dp, int64_t total_points);
+// Workspace layout of a filled shape holding total_points epochs (and the
+// lists of refine_units work units per curve of an FP64 confirmation).
+WorkspaceLayout workspace_layout(const DevPlan &dp, int64_t total_points,
+                                 int32_t refine_units = 0);
 // Point dp's workspace views into the block at `base`.
 void bind_workspace(DevPlan &dp, char *base, const WorkspaceLayout &lay);
 

@@ -422,6 +422,116 @@ hipError_t launch_epilogue(const DevPlan &dp, gce_best_t *out_best,
 }
 
 // ---------------------------------------------------------------------------
+// FP64 confirmation of a split search's minima (gce_opts.refine_units)
+// ---------------------------------------------------------------------------
+// One block per curve (schedule rank): the k work units with the smallest
+// (minimum CE, flat index) among the curve's units, in k rounds of a block
+// minimum over the units above the previous round's choice.  A curve with
+// fewer valid units than k repeats its last choice.
+__global__ __launch_bounds__(kEpiBlock) void k_refine_select(DevPlan dp, int32_t k,
+                                                             int64_t *list)
+{
+    __shared__ double sh_h[kEpiBlock / kWave];
+    __shared__ int64_t sh_f[kEpiBlock / kWave];
+    __shared__ int64_t sh_i[kEpiBlock / kWave];
+    const int64_t rank = blockIdx.x;
+    const int64_t base = rank * dp.units_per_curve;
+    const Partial *pp = dp.partials + base;
+    double prev_h = NAN;
+    int64_t prev_f = -1, prev_i = 0;
+    for (int32_t r = 0; r < k; ++r) {
+        double h = NAN;
+        int64_t f = -1, idx = -1;
+        for (int64_t i = threadIdx.x; i < dp.units_per_curve; i += kEpiBlock) {
+            const Partial v = pp[i];
+            if (r > 0 && !lex_less(prev_h, prev_f, v.h, v.flat)) continue;
+            if (lex_less(v.h, v.flat, h, f)) {
+                h = v.h;
+                f = v.flat;
+                idx = i;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ho = __shfl_xor(h, off, kWave);
+            const int64_t fo = __shfl_xor(f, off, kWave);
+            const int64_t io = __shfl_xor(idx, off, kWave);
+            if (lex_less(ho, fo, h, f)) {
+                h = ho;
+                f = fo;
+                idx = io;
+            }
+        }
+        const int w = threadIdx.x / kWave;
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            sh_h[w] = h;
+            sh_f[w] = f;
+            sh_i[w] = idx;
+        }
+        __syncthreads();
+        h = sh_h[0];
+        f = sh_f[0];
+        idx = sh_i[0];
+        for (int i = 1; i < kEpiBlock / kWave; ++i)
+            if (lex_less(sh_h[i], sh_f[i], h, f)) {
+                h = sh_h[i];
+                f = sh_f[i];
+                idx = sh_i[i];
+            }
+        __syncthreads();   // every thread has read this round's candidates
+        if (f >= 0) {
+            prev_h = h;
+            prev_f = f;
+            prev_i = idx;
+        }
+        if (threadIdx.x == 0) list[rank * k + r] = base + prev_i;
+    }
+}
+
+hipError_t launch_refine_select(const DevPlan &dp, int32_t k, int64_t *list, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_refine_select, dim3((unsigned)dp.n_curves), dim3(kEpiBlock), 0, s, dp,
+                       k, list);
+    return hipGetLastError();
+}
+
+// One thread per curve: the FP64 minimum over the curve's k confirmed units
+// replaces the reported minimum; the moments stay those of the split values.
+__global__ void k_refine_merge(DevPlan dp, int32_t k, const Partial *ref,
+                               gce_best_t *out_best)
+{
+    const int64_t rank = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rank >= dp.n_curves) return;
+    const int32_t c = dp.order[rank];
+    double h = NAN;
+    int64_t f = -1;
+    for (int32_t i = 0; i < k; ++i) {
+        const Partial v = ref[rank * k + i];
+        if (lex_less(v.h, v.flat, h, f)) {
+            h = v.h;
+            f = v.flat;
+        }
+    }
+    gce_best_t b = out_best[c];
+    if (b.flat_index < 0 || f < 0) return;   // an invalid curve stays as reported
+    b.flat_index = f;
+    b.period_index = (int32_t)(f % dp.n_p);
+    b.pdot_index = (int32_t)(f / dp.n_p);
+    b.ce_min = h;
+    b.significance = b.ce_std > 0.0 ? (b.ce_mean - h) / b.ce_std : 0.0;
+    out_best[c] = b;
+}
+
+hipError_t launch_refine_merge(const DevPlan &dp, int32_t k, const Partial *ref,
+                               gce_best_t *out_best, hipStream_t s)
+{
+    const int64_t blocks = (dp.n_curves + kEpiBlock - 1) / kEpiBlock;
+    hipLaunchKernelGGL(k_refine_merge, dim3((unsigned)blocks), dim3(kEpiBlock), 0, s, dp, k, ref,
+                       out_best);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // debug counts: one thread per requested trial, same binning as the search
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_debug_counts(

@@ -62,8 +62,10 @@ void k_search_co(DevPlan dp, void *out_ce_v)
     __syncthreads();   // table and cleared cells, before any wave adds or leaves
 
     // one unit per block (2-D launch: a dispatch counts work-items in 32 bits)
-    const int64_t u = dp.unit0 + (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (u >= dp.n_units) return;   // the same for both waves
+    // (or, with a unit list, entry unit0 + ... of the list)
+    const int64_t ui = dp.unit0 + (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (ui >= dp.n_units) return;   // the same for both waves
+    const int64_t u = dp.unit_list ? dp.unit_list[ui] : ui;
     const int64_t rank = u / dp.units_per_curve;
     const int64_t rem = u - rank * dp.units_per_curve;
     const int32_t g = (int32_t)(rem / dp.n_ptiles);
@@ -83,8 +85,8 @@ void k_search_co(DevPlan dp, void *out_ce_v)
                         out_ce[((int64_t)c * dp.n_pd + q0 + t) * dp.n_p + p] = (OutT)NAN;
             }
             if (lane == 0) {
-                dp.partials[u] = Partial{NAN, -1};
-                dp.stats[u] = UnitStats{0.0, 0.0, 0.0};
+                dp.partials[ui] = Partial{NAN, -1};
+                dp.stats[ui] = UnitStats{0.0, 0.0, 0.0};
             }
         }
         return;
@@ -360,8 +362,8 @@ void k_search_co(DevPlan dp, void *out_ce_v)
         }
     const double wm2 = wave_sum(lm2);
     if (lane == 0) {
-        dp.partials[u] = Partial{best_h, best_f};
-        dp.stats[u] = UnitStats{wcnt, wmean, wm2};
+        dp.partials[ui] = Partial{best_h, best_f};
+        dp.stats[ui] = UnitStats{wcnt, wmean, wm2};
     }
 }
 

@@ -147,6 +147,18 @@ def test_waves_per_unit_checked_on_host():
         assert ei.value.status == -6, (n_phase, tq)
 
 
+def test_refine_units_checked_on_host():
+    """refine_units is in [0, 64] (else GCE_EINVAL), refused before any
+    device call, whatever the precision."""
+    _ensure_built()
+    off = np.array([0, 5, 9])
+    for prec in (gce.PRECISION_FP64, gce.PRECISION_SPLIT_FP32):
+        for bad in (-1, 65, 1 << 20):
+            with pytest.raises(gce.GceError) as ei:
+                gce.Plan(off, 10, 8, 10, 5, precision=prec, refine_units=bad, device="cuda:0")
+            assert ei.value.status == -1, (prec, bad)
+
+
 def _write_inputs(d, w):
     w.times.astype("<f8").tofile(os.path.join(d, "times.f64"))
     w.mags.astype("<f8").tofile(os.path.join(d, "mags.f64"))
