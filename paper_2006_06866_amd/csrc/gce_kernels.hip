@@ -346,7 +346,9 @@ hipError_t launch_search(const DevPlan &dp, void *out_ce, hipStream_t s)
 // ---------------------------------------------------------------------------
 // epilogue: per-curve minimum over the curve's work units
 // ---------------------------------------------------------------------------
-constexpr int kEpiBlock = 256;
+// One block per curve reads all the curve's work units (1.3 M of them per
+// curve on the paper-scale grid): 1024 threads keep more loads in flight.
+constexpr int kEpiBlock = 1024;
 
 __global__ __launch_bounds__(kEpiBlock) void k_epilogue(DevPlan dp,
                                                         gce_best_t *out_best)
@@ -525,8 +527,9 @@ __global__ void k_refine_merge(DevPlan dp, int32_t k, const Partial *ref,
 hipError_t launch_refine_merge(const DevPlan &dp, int32_t k, const Partial *ref,
                                gce_best_t *out_best, hipStream_t s)
 {
-    const int64_t blocks = (dp.n_curves + kEpiBlock - 1) / kEpiBlock;
-    hipLaunchKernelGGL(k_refine_merge, dim3((unsigned)blocks), dim3(kEpiBlock), 0, s, dp, k, ref,
+    constexpr int kMergeBlock = 256;
+    const int64_t blocks = (dp.n_curves + kMergeBlock - 1) / kMergeBlock;
+    hipLaunchKernelGGL(k_refine_merge, dim3((unsigned)blocks), dim3(kMergeBlock), 0, s, dp, k, ref,
                        out_best);
     return hipGetLastError();
 }
