@@ -242,7 +242,10 @@ int gce_plan_create(gce_plan_t *plan, const int64_t *curve_offsets,
 /*
  * gce_plan_execute -- enqueue the whole search on `stream`: grid check,
  * per-curve preparation (t0, magnitude bins, points grouped by magnitude
- * bin), the search kernel, and the per-curve minimum.
+ * bin), the search kernel, and the per-curve minimum (for split plans with
+ * refine_units, then the FP64 search of each curve's best work units and
+ * the FP64 minimum over them).  Allocates nothing and copies nothing
+ * between host and device, so it can be captured in a HIP graph.
  *  times, mags : device, laid out as the plan's offsets describe.
  *  periods     : device, [n_periods].  pdots : device, [n_pdots].
  *  out_ce      : device cube [n_curves][n_pdots][n_periods] or NULL.
