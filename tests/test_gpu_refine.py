@@ -141,3 +141,36 @@ def test_refine_units_on_fp64_plans_change_nothing():
         bests.append(best.cpu().numpy())
         plan.close()
     assert np.array_equal(bests[0], bests[1])
+
+
+def test_refined_split_graph_replay_matches_eager():
+    """The whole split search with its FP64 confirmation captured once in a
+    HIP graph: every replay (with eager work and synchronisations between
+    them) gives the eager cube and minima bit for bit."""
+    w = synth.random_curves(79, [100, 500, 20, 64], n_freq=200, n_pdots=8)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 10, 5,
+                    precision=gce.PRECISION_SPLIT_FP32, refine_units=3)
+    ref_c, ref_b = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    ref_c, ref_b = ref_c.clone(), ref_b.clone()
+    cube, best = plan.new_cube(), plan.new_best()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.execute(t, m, P, Pd, out_ce=cube, out_best=best, stream=s)   # warm
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(t, m, P, Pd, out_ce=cube, out_best=best,
+                     stream=torch.cuda.current_stream())
+    for i in range(4):
+        cube.fill_(-1.0)
+        best.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(cube, ref_c), i
+        assert torch.equal(best.view(torch.int64), ref_b.view(torch.int64)), i
+    plan.close()
