@@ -174,3 +174,22 @@ def test_refined_split_graph_replay_matches_eager():
         assert torch.equal(cube, ref_c), i
         assert torch.equal(best.view(torch.int64), ref_b.view(torch.int64)), i
     plan.close()
+
+
+def test_refine_constant_and_invalid_curves():
+    """A one-epoch curve, a constant curve and a curve with a non-finite
+    magnitude beside a valid one: the confirmation leaves the invalid curve
+    invalid (flat -1, NaN CE), reports flat 0 with CE 0 for the constant
+    ones, and the FP64 plan's minimum for the valid one."""
+    w = synth.random_curves(80, [1, 40, 50, 300], n_freq=70, n_pdots=3)
+    w.mags[w.offsets[1]:w.offsets[2]] = 3.0
+    w.mags[w.offsets[2] + 3] = np.inf
+    runs = _plans(w, refine=2)
+    b64, br = runs[0][2], runs[2][2]
+    assert br["flat_index"][0] == 0 and br["flat_index"][1] == 0
+    assert br["ce_min"][0] == 0.0 and br["ce_min"][1] == 0.0
+    assert br["flat_index"][2] == -1 and np.isnan(br["ce_min"][2])
+    assert br["flat_index"][3] == b64["flat_index"][3]
+    assert abs(br["ce_min"][3] - b64["ce_min"][3]) <= 1e-14
+    for p, _, _ in runs:
+        p.close()
