@@ -193,3 +193,13 @@ def test_refine_constant_and_invalid_curves():
     assert abs(br["ce_min"][3] - b64["ce_min"][3]) <= 1e-14
     for p, _, _ in runs:
         p.close()
+
+
+@pytest.mark.parametrize("cfg", [2, 4, 5])
+def test_refine_full_workloads(cfg):
+    """The batched, ragged and long-baseline workloads at full size, minimum
+    only: with four confirmed units per curve the split path's minima are
+    the FP64 path's on every curve."""
+    w = synth.make_config(cfg)
+    say(f"[refine] full workload {cfg}: {w.n_curves} curves")
+    _check_against_fp64(w, _plans(w, refine=4, want_cube=False), f"config {cfg}")
