@@ -109,7 +109,7 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
                    chunk_periods: int, checkpoint: Optional[str] = None,
                    precision: int = 0, phase_overlap: bool = False,
                    trials_per_lane: int = 0, table_placement: int = 0,
-                   mag_overlap: bool = False,
+                   mag_overlap: bool = False, refine_units: int = 0,
                    want_cube: bool = False, on_range: Optional[Callable] = None,
                    stream=None) -> np.ndarray:
     """Minimum and statistics of every curve over the full (P, Pdot) grid,
@@ -118,7 +118,9 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
     times, mags, periods, pdots: float64 device tensors as for Plan.execute;
     offsets: host curve offsets.  Returns the merged [n_curves, 6] host
     array (read it with ``best_fields``).  With ``checkpoint`` set, progress
-    is saved after every range and a rerun resumes from it."""
+    is saved after every range and a rerun resumes from it.  refine_units
+    (split path): each range's minima confirmed in FP64 over each curve's
+    best work units of that range, as for Plan."""
     import torch
     from . import Plan, merge_results
 
@@ -127,9 +129,11 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
     if checkpoint:
         host = [np.asarray(offsets, dtype=np.int64)] + [
             x.detach().cpu().numpy() for x in (times, mags, periods, pdots)]
+        # a confirmation of the minima changes the results it checkpoints
+        extra = {"refine": int(refine_units)} if refine_units else {}
         fp = fingerprint(host, n_phase=int(n_phase), n_mag=int(n_mag),
                          precision=int(precision), phase_overlap=bool(phase_overlap),
-                         mag_overlap=bool(mag_overlap), chunk=int(chunk_periods))
+                         mag_overlap=bool(mag_overlap), chunk=int(chunk_periods), **extra)
     plans = {}
 
     def execute_range(p0, p1):
@@ -138,7 +142,7 @@ def search_chunked(times, mags, offsets, periods, pdots, n_phase: int, n_mag: in
             plans[n] = Plan(offsets, n, n_pd, n_phase, n_mag, precision=precision,
                             trials_per_lane=trials_per_lane, phase_overlap=phase_overlap,
                             table_placement=table_placement, mag_overlap=mag_overlap,
-                            device=times.device)
+                            refine_units=refine_units, device=times.device)
         plan = plans[n]
         cube = plan.new_cube() if want_cube else None
         cube, best = plan.execute(times, mags, periods[p0:p1], pdots, out_ce=cube,
