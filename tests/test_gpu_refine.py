@@ -203,3 +203,24 @@ def test_refine_full_workloads(cfg):
     w = synth.make_config(cfg)
     say(f"[refine] full workload {cfg}: {w.n_curves} curves")
     _check_against_fp64(w, _plans(w, refine=4, want_cube=False), f"config {cfg}")
+
+
+def test_refine_in_period_ranges():
+    """The chunked driver with the split path and the FP64 confirmation over
+    period ranges of a slice of the batched workload: the merged minima are
+    the FP64 path's one-launch minima, the merged CE values FP64 ones."""
+    from paper_2006_06866_amd import chunked
+    w = synth.make_config(2).subset(np.arange(8))
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag)
+    _, best = plan.execute(t, m, P, Pd)
+    torch.cuda.synchronize()
+    want = gce.best_fields(best)
+    plan.close()
+    acc = chunked.search_chunked(t, m, w.offsets, P, Pd, w.n_phase, w.n_mag, 6000,
+                                 precision=gce.PRECISION_SPLIT_FP32, refine_units=4)
+    got = gce.best_fields(acc)
+    assert np.array_equal(got["flat_index"], want["flat_index"])
+    tol = np.array([ce_tolerance(h, w.n_phase, w.n_mag, n) for h, n in
+                    zip(want["ce_min"], w.lengths)])
+    assert np.all(np.abs(got["ce_min"] - want["ce_min"]) <= tol)
