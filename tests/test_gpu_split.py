@@ -96,6 +96,39 @@ def test_split_overlap_self_consistent():
     say(f"[split] overlap band {band}")
 
 
+@pytest.mark.parametrize("co", [1, 2])
+def test_split_both_overlaps_in_band(co):
+    """Overlapping phase and magnitude bins at once, one and two waves per
+    unit: each CE value is Eq. (4) of its split histogram, which holds the
+    oracle's entries (two phase bins per epoch, one or two magnitude rows),
+    and the histogram differs from the oracle's only through band epochs."""
+    w = synth.random_curves(96 + co, [3, 64, 257, 900], n_freq=150, n_pdots=5,
+                            n_phase=20, n_mag=6, pdot_scale=5e-9)
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, w.n_phase, w.n_mag,
+                    precision=gce.PRECISION_SPLIT_FP32, phase_overlap=True,
+                    mag_overlap=True, waves_per_unit=co, trials_per_lane=4)
+    assert plan.info()["waves_per_unit"] == co
+    cube, _ = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    g = cube.cpu().numpy()
+    rng = np.random.default_rng(11 + co)
+    ci = rng.integers(0, w.n_curves, 400)
+    fi = rng.integers(0, w.periods.size * w.pdots.size, 400)
+    cnt = plan.debug_counts(t, m, P, Pd, ci, fi).cpu().numpy().astype(np.uint32)
+    _, want = oracle.trials(w.times, w.mags, w.offsets, w.periods, w.pdots, w.n_phase,
+                            w.n_mag, ci, fi, want_counts=True, phase_overlap=True,
+                            mag_overlap=True)
+    assert np.array_equal(cnt.sum(axis=(1, 2)), want.sum(axis=(1, 2)))
+    h_own = np.array([oracle.entropy(c) for c in cnt])
+    q, p = np.divmod(fi, w.periods.size)
+    assert np.all(np.abs(g[ci, q, p] - h_own) <= 2.0 ** -23 * np.abs(h_own) + 1e-12)
+    band = check_counts_in_band(w, ci, fi, cnt, want, phase_overlap=True, mag_overlap=True,
+                                label=f"both overlaps co={co}")
+    say(f"[split] both overlaps co={co} band {band}")
+    plan.close()
+
+
 def test_split_lds_limit_is_reported():
     # 128 phase bins: one trial pair's histogram and marginals fill 64 KiB of
     # LDS, as on the FP64 path; two pairs exceed it
