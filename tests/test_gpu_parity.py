@@ -634,6 +634,47 @@ def test_file_search_program_matches_oracle(tmp_path, flags, phase_overlap, mag_
                       count_mult=cm)
 
 
+def test_file_search_program_split_with_fp64_confirmation(tmp_path):
+    """The native program on the split path with 64 confirmed units per curve,
+    more than this grid's curves have: every reported minimum is searched
+    again in FP64, so it is the oracle's minimum (or ties it within the FP64
+    tolerance) with an FP64 CE value; the float cube and the results are
+    those of the same plan made through the Python binding, bit for bit."""
+    import os
+    import subprocess
+    from paper_2006_06866_amd import build as gbuild
+    w = synth.random_curves(181, EDGE_LENGTHS, n_freq=110, n_pdots=5, n_phase=15,
+                            n_mag=5, pdot_scale=5e-9)
+    d = str(tmp_path)
+    w.times.astype("<f8").tofile(os.path.join(d, "times.f64"))
+    w.mags.astype("<f8").tofile(os.path.join(d, "mags.f64"))
+    np.asarray(w.offsets, dtype="<i8").tofile(os.path.join(d, "offsets.i64"))
+    w.periods.astype("<f8").tofile(os.path.join(d, "periods.f64"))
+    w.pdots.astype("<f8").tofile(os.path.join(d, "pdots.f64"))
+    say("[file search] --split --refine-units 64")
+    r = subprocess.run([gbuild.FILE_SEARCH, d, "15", "5", "--cube", "--split",
+                        "--trials-per-lane", "4", "--refine-units", "64"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    cube = np.fromfile(os.path.join(d, "cube.f32"), dtype="<f4").reshape(
+        w.n_curves, w.pdots.size, w.periods.size)
+    assert not os.path.exists(os.path.join(d, "cube.f64"))
+    raw = np.fromfile(os.path.join(d, "best.bin"), dtype=np.uint8)
+    bf = gce.best_fields(raw)
+    oc, obf, obc = oracle.search(w.times, w.mags, w.offsets, w.periods, w.pdots, 15, 5)
+    # 110 periods x 5 Pdots at four trials per lane: 2 x 2 units per curve
+    assert_best_valid(bf["flat_index"], bf["ce_min"], obf, obc, oc, w, "file search refine")
+    t, m, P, Pd = upload(w)
+    plan = gce.Plan(w.offsets, w.periods.size, w.pdots.size, 15, 5,
+                    precision=gce.PRECISION_SPLIT_FP32, trials_per_lane=4, refine_units=64)
+    assert plan.info()["work_units"] == 4 * w.n_curves
+    pc, pb = plan.execute(t, m, P, Pd, out_ce=plan.new_cube())
+    torch.cuda.synchronize()
+    assert np.array_equal(cube.view(np.int32), pc.cpu().numpy().view(np.int32))
+    assert np.array_equal(raw, pb.cpu().numpy().view(np.uint8).ravel())
+    plan.close()
+
+
 def _aligned_curve_workload(n, n_phase, n_mag, seed):
     """A curve of n epochs at t = k / 8 d with two magnitude levels, plus a
     short noisy curve.  At P = 1/8 d and Pdot = 0 every epoch of the first
