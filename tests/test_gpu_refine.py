@@ -196,25 +196,29 @@ def test_refine_constant_and_invalid_curves():
         p.close()
 
 
+@pytest.mark.parametrize("k", [8, 64])
 @pytest.mark.parametrize("co", [1, 2])
-def test_refine_more_units_than_a_curve_has(co):
-    """k = 64, the largest accepted, on curves with fewer work units than
-    that: the selection repeats its last choice once a curve's units run
-    out, so every unit is searched again in FP64 and the reported minima are
-    the FP64 plan's trials with bit-identical CE values (the same kernel and
-    tiling, the c ln c table read from global memory instead of LDS, which
-    holds the same values).  k = 1 confirms the split minimum's unit alone."""
-    w = synth.random_curves(81, [1, 37, 64, 300, 900], n_freq=300, n_pdots=5,
+def test_refine_every_unit_of_a_curve(co, k):
+    """k at least the units a curve has (8 here: 200 periods in four tiles of
+    64 lanes, 5 Pdots in two groups of four): k = 8 takes every unit, k = 64
+    (the largest accepted) takes them all and then repeats its last choice
+    once the units run out.  Every unit is searched again in FP64, so the
+    reported minima are the FP64 plan's trials with bit-identical CE values
+    (the same kernel and tiling, the c ln c table read from global memory
+    instead of LDS, which holds the same values).  k - 1 leaves one unit
+    out: then only the FP64 value of the reported trial is required."""
+    w = synth.random_curves(81, [1, 37, 64, 300, 900], n_freq=200, n_pdots=5,
                             pdot_scale=5e-9)
-    runs = _plans(w, refine=64, tq=4, co=co)
+    runs = _plans(w, refine=k, tq=4, co=co)
     units = runs[2][0].info()["work_units"] // w.n_curves
-    say(f"[refine] k=64 over {units} units per curve, co={co}")
-    assert 1 <= units < 64
+    say(f"[refine] k={k} over {units} units per curve, co={co}")
+    assert units == 8
     b64, br = runs[0][2], runs[2][2]
     assert np.array_equal(br["flat_index"], b64["flat_index"])
     assert np.array_equal(br["ce_min"].view(np.int64), b64["ce_min"].view(np.int64))
-    _check_against_fp64(w, runs, f"k=64 co={co}")
-    _check_against_fp64(w, _plans(w, refine=1, tq=4, co=co), f"k=1 co={co}", strict=False)
+    _check_against_fp64(w, runs, f"k={k} co={co}")
+    _check_against_fp64(w, _plans(w, refine=k - 1, tq=4, co=co), f"k={k - 1} co={co}",
+                        strict=False)
 
 
 @pytest.mark.parametrize("cfg", [2, 4, 5])
